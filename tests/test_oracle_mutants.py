@@ -1,0 +1,59 @@
+"""Each plausible mistake planted in a copy of the oracle's C source must be
+caught by at least one pin.  The copies are built in a temporary directory
+on the CPU; the real oracle is untouched."""
+import os
+
+import pytest
+
+import oracle
+import pins
+
+# (name, original text, replacement): a dropped term, a wrong sign, a wrong
+# or transposed index, a wrong scale, a mistake in a closed form.
+MUTANTS = [
+    ("rx_ignored", "return 0.5 * (rt + rv);", "return 0.5 * (rt + rt);"),
+    ("full_path_not_half", "return 0.5 * (rt + rv);", "return (rt + rv);"),
+    ("doppler_sign", "double phi = (psi_f + th_f) - ph_f;", "double phi = (psi_f + th_f) + ph_f;"),
+    ("beat_sign", "double phi = (psi_f + th_f) - ph_f;", "double phi = (psi_f - th_f) - ph_f;"),
+    ("channel_transposed", "int m = c / r->N, rr = c % r->N;", "int m = c % r->M, rr = c / r->M;"),
+    ("beat_factor_two", "*Kb = (2.0 * r->mu) / (r->c0 * r->Fs);", "*Kb = (r->mu) / (r->c0 * r->Fs);"),
+    ("carrier_dropped", "*Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;", "*Kc = 0.0;"),
+    ("carrier_always", "*Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;",
+     "*Kc = (2.0 * r->fc) / r->c0;"),
+    ("doppler_no_Tb", "*Kd = ((2.0 * r->fc) * r->Tb) / r->c0;", "*Kd = (2.0 * r->fc) / r->c0;"),
+    ("n_off_by_one", "term(R, a, v, n, l, Kc, Kb, Kd, &re, &im);",
+     "term(R, a, v, n + 1, l, Kc, Kb, Kd, &re, &im);"),
+    ("l_off_by_one", "term(R, a, v, n, l, Kc, Kb, Kd, &re, &im);",
+     "term(R, a, v, n, l + 1, Kc, Kb, Kd, &re, &im);"),
+    ("n_l_swapped_in_phase", "double th_f = frac((R * Kb) * (double)n);",
+     "double th_f = frac((R * Kb) * (double)l);"),
+    ("amp_squared", "*re = a * cos(ang);\n    *im = a * sin(ang);",
+     "*re = a * a * cos(ang);\n    *im = a * a * sin(ang);"),
+    ("conjugate_output", "o[2 * n + 1] += im;", "o[2 * n + 1] -= im;"),
+    ("dz_uses_y", "double dz = (double)z - ant[2];", "double dz = (double)z - ant[1];"),
+    ("dropped_dz", "return sqrt((dx * dx + dy * dy) + dz * dz);", "return sqrt(dx * dx + dy * dy);"),
+    ("first_pixel_skipped", "for (int64_t p = 0; p < P; ++p) {", "for (int64_t p = 1; p < P; ++p) {"),
+    ("entries_n_l_swapped", "ns[k], ls[k], Kc, Kb, Kd", "ls[k] % r->Ns, ns[k] % r->L, Kc, Kb, Kd"),
+    ("marginal_l_sign", "geom(r->L, -beta, &gr, &gi);", "geom(r->L, beta, &gr, &gi);"),
+    ("marginal_n_length", "geom(r->Ns, b, &gr, &gi);", "geom(r->Ns - 1, b, &gr, &gi);"),
+    ("geom_phase_half", "double ang = PI * fmod((double)(N - 1) * xr, 2.0);",
+     "double ang = PI * fmod((double)N * xr, 2.0);"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, old, new):
+    src = open(oracle.SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    path = os.path.join(tmp_path, "mutant.c")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    lib = oracle.build(src=path, out=os.path.join(tmp_path, "libmutant.so"))
+    o = oracle.Oracle(lib)
+    caught = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(o)
+        except (AssertionError, ValueError, FloatingPointError):
+            caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every pin"
