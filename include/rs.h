@@ -1,0 +1,214 @@
+/*
+ * rs.h -- C ABI of librs, MI355X (gfx950) synthesis of FMCW TDM-MIMO beat
+ * cubes where every rendered pixel is a point scatterer.
+ *
+ * Signal model (Sec. II).  For an M-Tx / N-Rx array, eq. (1) gives the beat
+ * signal of Tx m and Rx r at fast-time sample n_s and TDM block l as a
+ * sigma-weighted exp(j 2 pi (2 mu R / c * (n_s - 1)/F_s - f_D (l - 1) T_b));
+ * eq. (2) sums that over the N_az x N_el rendered pixels.  This library keeps
+ * every virtual channel c = m*N + r separate and uses exact per-channel ranges
+ * (not eq. (2)'s far-field angle term), 0-based indices:
+ *
+ *   Y[c][l][n] = sum_p a_p exp(j 2 pi (psi_{p,c} + b_{p,c} n - beta_p l))
+ *
+ *   R_{p,c}   = (|x_p - tx_m| + |x_p - rx_r|) / 2       (eq. (1)'s R_{m,n})
+ *   psi_{p,c} = 2 fc R_{p,c} / c0   carrier phase carried by sigma; 0 when
+ *                                    rs_radar.carrier_phase == 0 (sigma = a)
+ *   b_{p,c}   = 2 mu R_{p,c} / (c0 Fs)   beat frequency, cycles per sample
+ *   beta_p    = 2 fc v_p Tb / c0         Doppler f_D = 2 v fc / c0 times T_b
+ *
+ * a_p is the pixel strength (eq. (2)'s P_r, applied as an amplitude) and v_p
+ * its radial velocity (eq. (2)'s V), positive when approaching.  T_b is the
+ * TDM block period (one block holds M chirps).  The intra-block Tx slot
+ * offset, residual video phase and intra-chirp Doppler are not in eq. (1)
+ * and are not modelled.
+ *
+ * Two forms compute Y:
+ *   RS_FORM_FP64_DIRECT   binary64 phasors and binary64 complex
+ *                         multiply-accumulate on the vector ALUs;
+ *   RS_FORM_MFMA_SPLIT16  binary64 phase arguments reduced mod 1, binary32
+ *                         phasors split into hi + lo binary16 parts, and the
+ *                         per-channel complex contraction
+ *                         Y_c = F_c^T diag(sigma_c) D done on fp16 matrix
+ *                         cores with fp32 accumulation (hi*hi + hi*lo +
+ *                         lo*hi).  Typical relative L2 error vs an exact
+ *                         binary64 sum: 1e-6 .. 1e-5.
+ *
+ * Conventions
+ *   - Every call returns rs_status; nothing throws or aborts across the ABI.
+ *     rs_last_error() gives thread-local text for the last non-OK status.
+ *   - Pixel and cube buffers are caller-owned DEVICE memory on the plan's
+ *     device.  Calls taking a `hip_stream` (a hipStream_t, NULL = the null
+ *     stream) only enqueue work: buffers must stay valid until the stream has
+ *     passed the work.
+ *   - Cube layout: [C = M*N][L][Ns] row-major, n fastest, interleaved
+ *     (re, im); complex64 (2 x float32) or complex128 (2 x float64).
+ *   - Pixel positions are metres in the radar frame, float32 structure of
+ *     arrays.  Per-pixel values are not validated (NaN in gives NaN out).
+ *     Aliasing is not an error: beat frequencies above Fs and |f_D T_b| > 1/2
+ *     wrap as the equation defines.
+ *   - P = 0 is valid and writes an exact zero cube.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RS_OK = 0,
+    RS_E_INVALID = 1,     /* bad argument; nothing was launched or written      */
+    RS_E_NOMEM = 2,       /* device or host allocation failed                   */
+    RS_E_DEVICE = 3,      /* a HIP runtime call failed (text: rs_last_error)     */
+    RS_E_UNSUPPORTED = 4, /* valid request this build cannot serve               */
+    RS_E_BUSY = 5,        /* session queue full (back-pressure); retry later     */
+    RS_E_NOT_FOUND = 6    /* unknown session ticket                              */
+} rs_status;
+
+typedef enum { RS_FORM_FP64_DIRECT = 0, RS_FORM_MFMA_SPLIT16 = 1 } rs_form;
+typedef enum { RS_C64 = 0, RS_C128 = 1 } rs_dtype; /* interleaved (re, im) */
+
+/* eq. (1) signal model, SI units.  tx_xyz / rx_xyz are HOST arrays
+ * [M][3] / [N][3] of antenna positions in metres; they are copied by
+ * rs_cube_plan and may be freed on return. */
+typedef struct {
+    int32_t M, N, Ns, L;     /* Tx, Rx, fast-time samples, TDM blocks (>= 1)   */
+    double fc, mu, Fs, Tb, c0; /* Hz, Hz/s, Hz, s, m/s (Fs, Tb, c0 > 0)        */
+    const double *tx_xyz, *rx_xyz;
+    int32_t carrier_phase;   /* 1: sigma = a exp(j 2 pi 2 fc R / c0); 0: a     */
+} rs_radar;
+
+/* One frame of rendered pixels, caller-owned DEVICE pointers, float32 SoA. */
+typedef struct {
+    int64_t P; /* >= 0; pointers may be NULL when P == 0 */
+    const float *x, *y, *z, *amp, *vr;
+} rs_pixels;
+
+typedef struct rs_plan rs_plan;
+typedef struct rs_session rs_session;
+
+/* ---------------------------------------------------------------- plans -- */
+
+/* Validate `radar`, derive the phase constants, copy the antenna geometry to
+ * the current HIP device and choose the tile configuration.  max_pixels
+ * bounds P for every later call on this plan (>= 0).
+ * Errors: RS_E_INVALID (M, N, Ns or L < 1, M*N*L*Ns > 2^31, Fs, Tb or c0 <= 0,
+ * any non-finite parameter, NULL tx/rx, bad form or dtype, max_pixels < 0),
+ * RS_E_NOMEM, RS_E_DEVICE.  On success *out owns device memory until
+ * rs_plan_destroy.  A plan is immutable and may be used from several threads
+ * and streams at once. */
+rs_status rs_cube_plan(const rs_radar *radar, rs_form form, rs_dtype dtype,
+                       int64_t max_pixels, rs_plan **out);
+
+/* Bytes of device workspace rs_beat_synthesize_ws needs for P pixels
+ * (0 <= P <= max_pixels).  Errors: RS_E_INVALID. */
+rs_status rs_plan_workspace_bytes(const rs_plan *plan, int64_t P, size_t *bytes);
+
+/* Human-readable description of the plan (form, tile, chunking) into buf
+ * (always NUL-terminated when len > 0).  Errors: RS_E_INVALID. */
+rs_status rs_plan_describe(const rs_plan *plan, int64_t P, char *buf, size_t len);
+
+/* Enqueue the synthesis of one cube on `hip_stream`.  Split-K workspace is
+ * taken from the device's stream-ordered pool and returned in stream order.
+ * Errors: RS_E_INVALID (NULL plan/pixels/cube, P < 0 or > max_pixels, NULL
+ * pixel pointer with P > 0), RS_E_NOMEM, RS_E_DEVICE. */
+rs_status rs_beat_synthesize(rs_plan *plan, const rs_pixels *pixels, void *cube,
+                             void *hip_stream);
+
+/* As rs_beat_synthesize with caller-provided device workspace of at least
+ * rs_plan_workspace_bytes(plan, P) bytes (256-byte aligned).  The workspace
+ * must not be used by other work until the stream has passed this call. */
+rs_status rs_beat_synthesize_ws(rs_plan *plan, const rs_pixels *pixels, void *cube,
+                                void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Enqueue `nframes` cubes that share one plan (e.g. consecutive animation
+ * frames with different pixel counts) as ONE persistent launch over all
+ * frames' work items plus one reduction launch.  frames: HOST array of
+ * nframes rs_pixels (device pointers inside); cubes: device buffer of
+ * nframes consecutive cubes.  Each frame's cube is bitwise identical to
+ * rs_beat_synthesize on that frame alone.
+ * Errors: as rs_beat_synthesize, plus nframes < 0. */
+rs_status rs_beat_synthesize_batch(rs_plan *plan, const rs_pixels *frames, int32_t nframes,
+                                   void *cubes, void *hip_stream);
+
+void rs_plan_destroy(rs_plan *plan);
+
+/* ------------------------------------------------------------- sessions -- */
+/* A session is a serving loop with continuous batching: a scheduler thread
+ * admits queued cube requests while the admitted HBM footprint stays within
+ * hbm_budget and a slot is free, slices every admitted request into fixed
+ * pixel-chunk work items, and runs persistent MFMA-form launches that mix
+ * work items of all admitted requests.  A request that arrives while others
+ * run is admitted as soon as memory and a slot free up.  A request's cube is
+ * bitwise identical whatever else runs beside it. */
+
+typedef struct {
+    int32_t device;       /* HIP device ordinal                                  */
+    size_t hbm_budget;    /* bytes of session workspace (partial sums) in flight */
+    int32_t max_slots;    /* requests admitted at once (>= 1)                    */
+    int32_t queue_cap;    /* requests queued before submit returns RS_E_BUSY     */
+    int32_t slice_items;  /* work items per launch, 0 = automatic                */
+} rs_session_opts;
+
+typedef enum {
+    RS_REQ_QUEUED = 0, RS_REQ_RUNNING = 1, RS_REQ_DONE = 2, RS_REQ_FAILED = 3,
+    RS_REQ_CANCELLED = 4
+} rs_request_state;
+
+typedef struct {
+    int64_t t_submit_ns, t_admit_ns, t_done_ns; /* host CLOCK_MONOTONIC */
+} rs_timing;
+
+typedef struct {
+    int64_t submitted, admitted, done, failed, cancelled, launches;
+    int64_t queued_now, running_now;
+    size_t footprint_now, footprint_peak;
+    double terms_done;
+} rs_session_stats;
+
+/* Start a session and its scheduler thread on opts->device.
+ * Errors: RS_E_INVALID (bad options), RS_E_NOMEM, RS_E_DEVICE. */
+rs_status rs_session_create(const rs_session_opts *opts, rs_session **out);
+
+/* Queue one request: synthesize `pixels` with `plan` (which must use
+ * RS_FORM_MFMA_SPLIT16 and outlive the request) into `cube`.  The pixel and
+ * cube device buffers are borrowed until poll reports DONE, FAILED or
+ * CANCELLED; pixel data must already be complete on the device.
+ * Errors: RS_E_INVALID (bad arguments, or a footprint that can never fit
+ * hbm_budget), RS_E_BUSY (queue full), RS_E_UNSUPPORTED (plan form). */
+rs_status rs_session_submit(rs_session *s, const rs_plan *plan, const rs_pixels *pixels,
+                            void *cube, uint64_t *ticket);
+
+/* State of a ticket (rs_request_state) and its timestamps (timing may be
+ * NULL).  Errors: RS_E_NOT_FOUND. */
+rs_status rs_session_poll(rs_session *s, uint64_t ticket, int32_t *state, rs_timing *timing);
+
+/* Cancel a request that is still queued.  Errors: RS_E_NOT_FOUND,
+ * RS_E_BUSY (already admitted). */
+rs_status rs_session_cancel(rs_session *s, uint64_t ticket);
+
+/* Block until every submitted request has finished. */
+rs_status rs_session_drain(rs_session *s);
+
+rs_status rs_session_stats_get(rs_session *s, rs_session_stats *out);
+
+/* Drain, stop the scheduler thread and free the session. */
+void rs_session_destroy(rs_session *s);
+
+/* Test hook: make the next `count` launches of this session report failure
+ * without running, so their requests end FAILED (host-side; no kernel is
+ * affected). */
+rs_status rs_session_inject_failure(rs_session *s, int32_t count);
+
+/* ---------------------------------------------------------------- misc -- */
+const char *rs_last_error(void);
+const char *rs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RS_H */

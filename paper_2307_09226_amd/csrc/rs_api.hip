@@ -1,0 +1,405 @@
+// Host side of the C ABI (include/rs.h): plans, single-frame and batched
+// synthesis.  All device work is enqueued on the caller's stream.
+#include "rs_api_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+static thread_local std::string tl_error;
+
+rs_status rs_fail(rs_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    tl_error = buf;
+    return s;
+}
+
+extern "C" const char *rs_last_error(void) { return tl_error.c_str(); }
+extern "C" const char *rs_version(void) { return "rs 0.1 gfx950"; }
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int round_up(int64_t v, int m) { return (int)(((v + m - 1) / m) * m); }
+
+// Restores the caller's current device on scope exit.
+struct device_guard {
+    int prev = -1;
+    rs_status st = RS_OK;
+    explicit device_guard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev && hipSetDevice(dev) != hipSuccess)
+            st = rs_fail(RS_E_DEVICE, "hipSetDevice(%d) failed", dev);
+    }
+    ~device_guard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- plans ----
+
+rs_status rs_plan_chunking(const rs_plan *pl, int64_t P, int32_t *S, int32_t *chunk)
+{
+    if (P <= 0) {
+        *S = 0;
+        *chunk = pl->min_chunk;
+        return RS_OK;
+    }
+    const int64_t tiles = (int64_t)pl->C * pl->n_tiles * pl->l_tiles;
+    int64_t s_target = pl->items_target / tiles;
+    if (s_target < 1) s_target = 1;
+    int64_t ch = (P + s_target - 1) / s_target;
+    ch = round_up(ch, 16);
+    if (ch < pl->min_chunk) ch = pl->min_chunk;
+    if (ch > (int64_t)1 << 30) return rs_fail(RS_E_INVALID, "pixel count too large");
+    *chunk = (int32_t)ch;
+    *S = (int32_t)((P + ch - 1) / ch);
+    return RS_OK;
+}
+
+size_t rs_partial_bytes(const rs_plan *pl, int32_t S)
+{
+    const size_t elem = pl->form == RS_FORM_FP64_DIRECT ? 16 : 8;
+    const size_t b = (size_t)S * pl->C * pl->L * pl->Ns * elem;
+    return (b + 255) & ~(size_t)255;
+}
+
+rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *partial,
+                   int32_t S, int32_t chunk)
+{
+    rs_job j;
+    std::memset(&j, 0, sizeof j);
+    j.x = px->x;
+    j.y = px->y;
+    j.z = px->z;
+    j.amp = px->amp;
+    j.vr = px->vr;
+    j.P = px->P;
+    j.cube = cube;
+    j.partial = partial;
+    j.ant = pl->d_ant;
+    j.Kc = pl->Kc;
+    j.Kb = pl->Kb;
+    j.Kd = pl->Kd;
+    j.M = pl->M;
+    j.N = pl->N;
+    j.Ns = pl->Ns;
+    j.L = pl->L;
+    j.n_tiles = pl->n_tiles;
+    j.l_tiles = pl->l_tiles;
+    j.S = S;
+    j.chunk = chunk;
+    j.item_count = (int64_t)S * pl->C * pl->n_tiles * pl->l_tiles;
+    j.dtype = pl->dtype == RS_C128 ? 1 : 0;
+    return j;
+}
+
+rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px)
+{
+    if (!px) return rs_fail(RS_E_INVALID, "pixels is NULL");
+    if (px->P < 0) return rs_fail(RS_E_INVALID, "P < 0");
+    if (px->P > pl->max_pixels)
+        return rs_fail(RS_E_INVALID, "P = %lld exceeds the plan's max_pixels = %lld",
+                       (long long)px->P, (long long)pl->max_pixels);
+    if (px->P > 0 && (!px->x || !px->y || !px->z || !px->amp || !px->vr))
+        return rs_fail(RS_E_INVALID, "NULL pixel array with P > 0");
+    return RS_OK;
+}
+
+rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, int grid, hipStream_t st)
+{
+    if (L.total <= 0) return RS_OK;
+    if (pl->form == RS_FORM_FP64_DIRECT)
+        rs_launch_plain(L, pl->tl, grid, st);
+    else
+        rs_launch_mfma(L, pl->wn, pl->tl, grid, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "main kernel launch: %s", hipGetErrorString(e));
+    return RS_OK;
+}
+
+rs_status rs_launch_reduce_checked(const rs_plan *pl, const rs_launch &L, hipStream_t st)
+{
+    rs_launch_reduce(L, pl->form == RS_FORM_FP64_DIRECT ? 0 : 1, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "reduce launch: %s", hipGetErrorString(e));
+    return RS_OK;
+}
+
+extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtype,
+                                  int64_t max_pixels, rs_plan **out)
+{
+    if (!out) return rs_fail(RS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!r) return rs_fail(RS_E_INVALID, "radar is NULL");
+    if (r->M < 1 || r->N < 1 || r->Ns < 1 || r->L < 1)
+        return rs_fail(RS_E_INVALID, "M, N, Ns and L must be >= 1");
+    const int64_t cells = (int64_t)r->M * r->N * r->L * r->Ns;
+    if (cells > ((int64_t)1 << 31)) return rs_fail(RS_E_INVALID, "cube larger than 2^31 entries");
+    if (r->M > 256 || r->N > 256) return rs_fail(RS_E_INVALID, "at most 256 Tx and 256 Rx");
+    if (!finite_pos(r->Fs) || !finite_pos(r->Tb) || !finite_pos(r->c0))
+        return rs_fail(RS_E_INVALID, "Fs, Tb and c0 must be finite and > 0");
+    if (!std::isfinite(r->fc) || !std::isfinite(r->mu))
+        return rs_fail(RS_E_INVALID, "fc and mu must be finite");
+    if (!r->tx_xyz || !r->rx_xyz) return rs_fail(RS_E_INVALID, "tx_xyz / rx_xyz is NULL");
+    for (int i = 0; i < 3 * r->M; ++i)
+        if (!std::isfinite(r->tx_xyz[i])) return rs_fail(RS_E_INVALID, "non-finite Tx position");
+    for (int i = 0; i < 3 * r->N; ++i)
+        if (!std::isfinite(r->rx_xyz[i])) return rs_fail(RS_E_INVALID, "non-finite Rx position");
+    if (form != RS_FORM_FP64_DIRECT && form != RS_FORM_MFMA_SPLIT16)
+        return rs_fail(RS_E_INVALID, "unknown form");
+    if (dtype != RS_C64 && dtype != RS_C128) return rs_fail(RS_E_INVALID, "unknown dtype");
+    if (max_pixels < 0) return rs_fail(RS_E_INVALID, "max_pixels < 0");
+    if (max_pixels > ((int64_t)1 << 40)) return rs_fail(RS_E_INVALID, "max_pixels too large");
+
+    rs_plan *pl = new (std::nothrow) rs_plan();
+    if (!pl) return rs_fail(RS_E_NOMEM, "host allocation failed");
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        return rs_fail(RS_E_DEVICE, "no HIP device");
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess ||
+        ncu <= 0) {
+        delete pl;
+        return rs_fail(RS_E_DEVICE, "cannot query the compute-unit count");
+    }
+    pl->ncu = ncu;
+    pl->M = r->M;
+    pl->N = r->N;
+    pl->C = r->M * r->N;
+    pl->Ns = r->Ns;
+    pl->L = r->L;
+    pl->fc = r->fc;
+    pl->mu = r->mu;
+    pl->Fs = r->Fs;
+    pl->Tb = r->Tb;
+    pl->c0 = r->c0;
+    pl->carrier = r->carrier_phase ? 1 : 0;
+    // binary64 phase constants of the recipe (same expressions as the
+    // reference definition: Kc = 2 fc / c0, Kb = 2 mu / (c0 Fs),
+    // Kd = 2 fc Tb / c0)
+    pl->Kc = pl->carrier ? (2.0 * r->fc) / r->c0 : 0.0;
+    pl->Kb = (2.0 * r->mu) / (r->c0 * r->Fs);
+    pl->Kd = ((2.0 * r->fc) * r->Tb) / r->c0;
+    pl->form = form;
+    pl->dtype = dtype;
+    pl->max_pixels = max_pixels;
+    rs_choose_tiles(pl);
+
+    std::vector<double> ant(3 * (r->M + r->N));
+    std::memcpy(ant.data(), r->tx_xyz, sizeof(double) * 3 * r->M);
+    std::memcpy(ant.data() + 3 * r->M, r->rx_xyz, sizeof(double) * 3 * r->N);
+    if (hipMalloc(&pl->d_ant, ant.size() * sizeof(double)) != hipSuccess) {
+        delete pl;
+        return rs_fail(RS_E_NOMEM, "hipMalloc of the antenna table failed");
+    }
+    if (hipMemcpy(pl->d_ant, ant.data(), ant.size() * sizeof(double), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        (void)hipFree(pl->d_ant);
+        delete pl;
+        return rs_fail(RS_E_DEVICE, "copy of the antenna table failed");
+    }
+    *out = pl;
+    return RS_OK;
+}
+
+void rs_choose_tiles(rs_plan *pl)
+{
+    if (pl->form == RS_FORM_FP64_DIRECT) {
+        pl->tn = 64;
+        pl->tl = pl->L <= 64 ? 64 : 128;
+        pl->wn = 0;
+        pl->items_target = (int64_t)pl->ncu * 4;
+        pl->min_chunk = 256;
+        pl->occupancy = 2;
+    } else {
+        pl->tl = pl->L <= 64 ? 64 : 128;
+        const int max_wn = pl->tl == 64 ? 128 : 64;  // 256 fp32 accumulators per lane
+        int need = (pl->Ns + 3) / 4;                 // rows per wave to cover Ns
+        int wn = 32;
+        while (wn < need && wn < max_wn) wn *= 2;
+        pl->wn = wn;
+        pl->tn = 4 * wn;
+        pl->items_target = pl->ncu;
+        pl->min_chunk = 1024;
+        pl->occupancy = 1;
+    }
+    pl->n_tiles = (pl->Ns + pl->tn - 1) / pl->tn;
+    pl->l_tiles = (pl->L + pl->tl - 1) / pl->tl;
+}
+
+extern "C" void rs_plan_destroy(rs_plan *pl)
+{
+    if (!pl) return;
+    if (pl->d_ant) {
+        device_guard g(pl->device);
+        (void)hipFree(pl->d_ant);
+    }
+    delete pl;
+}
+
+extern "C" rs_status rs_plan_workspace_bytes(const rs_plan *pl, int64_t P, size_t *bytes)
+{
+    if (!pl || !bytes) return rs_fail(RS_E_INVALID, "NULL argument");
+    if (P < 0 || P > pl->max_pixels) return rs_fail(RS_E_INVALID, "P out of range");
+    int32_t S, chunk;
+    rs_status s = rs_plan_chunking(pl, P, &S, &chunk);
+    if (s != RS_OK) return s;
+    *bytes = rs_partial_bytes(pl, S);
+    return RS_OK;
+}
+
+extern "C" rs_status rs_plan_describe(const rs_plan *pl, int64_t P, char *buf, size_t len)
+{
+    if (!pl || !buf) return rs_fail(RS_E_INVALID, "NULL argument");
+    if (P < 0) return rs_fail(RS_E_INVALID, "P < 0");
+    int32_t S = 0, chunk = 0;
+    rs_status s = rs_plan_chunking(pl, P, &S, &chunk);
+    if (s != RS_OK) return s;
+    if (len == 0) return RS_OK;
+    snprintf(buf, len,
+             "{\"form\": \"%s\", \"dtype\": \"%s\", \"C\": %d, \"Ns\": %d, \"L\": %d, "
+             "\"tile_n\": %d, \"tile_l\": %d, \"wave_rows\": %d, \"n_tiles\": %d, \"l_tiles\": %d, "
+             "\"chunks\": %d, \"chunk_pixels\": %d, \"items\": %lld, \"cus\": %d}",
+             pl->form == RS_FORM_FP64_DIRECT ? "fp64_direct" : "mfma_split16",
+             pl->dtype == RS_C128 ? "complex128" : "complex64", pl->C, pl->Ns, pl->L, pl->tn,
+             pl->tl, pl->wn, pl->n_tiles, pl->l_tiles, S, chunk,
+             (long long)S * pl->C * pl->n_tiles * pl->l_tiles, pl->ncu);
+    return RS_OK;
+}
+
+// ------------------------------------------------------------ synthesis ----
+
+extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, void *cube,
+                                           void *ws, size_t ws_bytes, void *stream)
+{
+    if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
+    if (!cube) return rs_fail(RS_E_INVALID, "cube is NULL");
+    rs_status s = rs_check_pixels(pl, px);
+    if (s != RS_OK) return s;
+    int32_t S, chunk;
+    if ((s = rs_plan_chunking(pl, px->P, &S, &chunk)) != RS_OK) return s;
+    const size_t need = rs_partial_bytes(pl, S);
+    if (need > 0 && (!ws || ws_bytes < need))
+        return rs_fail(RS_E_INVALID, "workspace too small: need %zu bytes", need);
+    if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 255))
+        return rs_fail(RS_E_INVALID, "workspace must be 256-byte aligned");
+    device_guard g(pl->device);
+    if (g.st != RS_OK) return g.st;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+
+    rs_launch L;
+    std::memset(&L, 0, sizeof L);
+    L.inline_job = rs_make_job(pl, px, cube, ws, S, chunk);
+    L.njobs = 1;
+    L.total = L.inline_job.item_count;
+    if ((s = rs_launch_main(pl, L, (int)L.total, st)) != RS_OK) return s;
+    rs_launch R = L;
+    R.total = (int64_t)pl->C * pl->L * pl->Ns;
+    R.counter = nullptr;
+    return rs_launch_reduce_checked(pl, R, st);
+}
+
+extern "C" rs_status rs_beat_synthesize(rs_plan *pl, const rs_pixels *px, void *cube, void *stream)
+{
+    if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
+    if (!cube) return rs_fail(RS_E_INVALID, "cube is NULL");
+    rs_status s = rs_check_pixels(pl, px);
+    if (s != RS_OK) return s;
+    size_t need = 0;
+    if ((s = rs_plan_workspace_bytes(pl, px->P, &need)) != RS_OK) return s;
+    device_guard g(pl->device);
+    if (g.st != RS_OK) return g.st;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    if (need > 0 && hipMallocAsync(&ws, need, st) != hipSuccess)
+        return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", need);
+    s = rs_beat_synthesize_ws(pl, px, cube, ws, need, stream);
+    if (ws) {
+        hipError_t e = hipFreeAsync(ws, st);
+        if (e != hipSuccess && s == RS_OK) s = rs_fail(RS_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+    }
+    return s;
+}
+
+extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *frames, int32_t nframes,
+                                              void *cubes, void *stream)
+{
+    if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
+    if (nframes < 0) return rs_fail(RS_E_INVALID, "nframes < 0");
+    if (nframes == 0) return RS_OK;
+    if (!frames || !cubes) return rs_fail(RS_E_INVALID, "NULL frames or cubes");
+    rs_status s;
+    for (int f = 0; f < nframes; ++f)
+        if ((s = rs_check_pixels(pl, &frames[f])) != RS_OK) return s;
+    device_guard g(pl->device);
+    if (g.st != RS_OK) return g.st;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+
+    const size_t cube_bytes = (size_t)pl->C * pl->L * pl->Ns * (pl->dtype == RS_C128 ? 16 : 8);
+    std::vector<rs_job> jobs(nframes);
+    const size_t head = 256 + (((size_t)nframes * sizeof(rs_job) + 255) & ~(size_t)255);
+    size_t off = head;
+    int64_t items = 0, outs = 0;
+    for (int f = 0; f < nframes; ++f) {
+        int32_t S, chunk;
+        if ((s = rs_plan_chunking(pl, frames[f].P, &S, &chunk)) != RS_OK) return s;
+        jobs[f] = rs_make_job(pl, &frames[f], static_cast<char *>(cubes) + f * cube_bytes,
+                              reinterpret_cast<void *>(off), S, chunk);
+        jobs[f].item_begin = items;
+        jobs[f].out_begin = outs;
+        items += jobs[f].item_count;
+        outs += (int64_t)pl->C * pl->L * pl->Ns;
+        off += rs_partial_bytes(pl, S);
+    }
+    char *ws = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&ws), off, st) != hipSuccess)
+        return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", off);
+    for (auto &j : jobs) j.partial = ws + reinterpret_cast<uintptr_t>(j.partial);
+    rs_job *djobs = reinterpret_cast<rs_job *>(ws + 256);
+    // The host job table is pageable: the runtime stages it before returning.
+    hipError_t e = hipMemcpyAsync(djobs, jobs.data(), jobs.size() * sizeof(rs_job),
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(ws, st);
+        return rs_fail(RS_E_DEVICE, "job table copy: %s", hipGetErrorString(e));
+    }
+    rs_launch L;
+    std::memset(&L, 0, sizeof L);
+    L.jobs = djobs;
+    L.njobs = nframes;
+    L.total = items;
+    L.counter = reinterpret_cast<int *>(ws);
+    s = RS_OK;
+    if (items > 0) {
+        rs_launch_zero_int(L.counter, 1, st);
+        int64_t grid = (int64_t)pl->ncu * pl->occupancy;
+        if (grid > items) grid = items;
+        s = rs_launch_main(pl, L, (int)grid, st);
+    }
+    if (s == RS_OK) {
+        rs_launch R = L;
+        R.counter = nullptr;
+        R.total = outs;
+        s = rs_launch_reduce_checked(pl, R, st);
+    }
+    e = hipFreeAsync(ws, st);
+    if (e != hipSuccess && s == RS_OK) s = rs_fail(RS_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+    return s;
+}

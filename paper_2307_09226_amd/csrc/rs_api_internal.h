@@ -1,0 +1,32 @@
+// Host-side internals shared by rs_api.hip and rs_session.hip.
+#pragma once
+#include "../../include/rs.h"
+#include "rs_internal.h"
+
+struct rs_plan {
+    int device = 0;
+    int ncu = 0;
+    int32_t M = 0, N = 0, C = 0, Ns = 0, L = 0, carrier = 1;
+    double fc = 0, mu = 0, Fs = 0, Tb = 0, c0 = 0;
+    double Kc = 0, Kb = 0, Kd = 0;  // binary64 phase constants
+    double *d_ant = nullptr;        // device tx[M][3] then rx[N][3]
+    rs_form form = RS_FORM_MFMA_SPLIT16;
+    rs_dtype dtype = RS_C64;
+    int64_t max_pixels = 0;
+    // tile configuration
+    int tn = 0, tl = 0, wn = 0;     // tile rows (n), tile columns (l), rows per wave (MFMA)
+    int n_tiles = 0, l_tiles = 0;
+    int64_t items_target = 0;       // work items aimed at for one cube
+    int min_chunk = 0;              // smallest pixel chunk
+    int occupancy = 1;              // resident workgroups per CU of the main kernel
+};
+
+rs_status rs_fail(rs_status s, const char *fmt, ...);
+void rs_choose_tiles(rs_plan *pl);
+rs_status rs_plan_chunking(const rs_plan *pl, int64_t P, int32_t *S, int32_t *chunk);
+size_t rs_partial_bytes(const rs_plan *pl, int32_t S);
+rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *partial,
+                   int32_t S, int32_t chunk);
+rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px);
+rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, int grid, hipStream_t st);
+rs_status rs_launch_reduce_checked(const rs_plan *pl, const rs_launch &L, hipStream_t st);

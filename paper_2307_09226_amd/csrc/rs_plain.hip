@@ -1,0 +1,133 @@
+// Plain form: binary64 direct sum on the vector ALUs (gfx950).
+//
+// Y[c][l][n] = sum_p a_p exp(j2pi(psi_{p,c} + b_{p,c} n - beta_p l))  (Sec. II,
+// eq. (1) per virtual channel, pixel sum of eq. (2)).  Each term is the
+// product F[p][n] * D[p][l] with
+//   F[p][n] = exp(j2pi wrap(psi_f + frac(b n)))      (binary64 sincospi)
+//   D[p][l] = a_p exp(-j2pi frac(beta l))             (binary64 sincospi)
+// and is accumulated with four binary64 FMAs (8 flop per term).
+//
+// Work item = (channel, 64-row n tile, TL-column l tile, pixel chunk).  Per
+// step of 16 pixels the workgroup evaluates the 16 x 64 F and 16 x TL D
+// phasors once into LDS; each thread then owns a 4 (n) x TL/16 (l) block of
+// binary64 accumulators.  Chunks write binary64 partial tiles that the
+// reduce kernel sums in a fixed order.
+#include "rs_device.h"
+
+namespace {
+
+constexpr int kTN = 64;  // n rows per tile
+constexpr int kKP = 16;  // pixels per step
+
+template <int TL>
+__global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
+{
+    constexpr int NJ = TL / 16;
+    __shared__ double2 sF[kKP][kTN];
+    __shared__ double2 sD[kKP][TL];
+    __shared__ double sPsi[kKP], sB[kKP], sBeta[kKP], sA[kKP];
+    __shared__ int64_t s_item;
+
+    const int tid = threadIdx.x;
+    const int tn = tid & 15, tl = tid >> 4;
+    bool first = true;
+    for (;;) {
+        const int64_t item = rs_next_item(Lc, &s_item, first);
+        first = false;
+        if (item < 0) break;
+        const int jidx = rs_find_job<false>(Lc, item);
+        const rs_job &J = rs_job_of(Lc, jidx);
+        const rs_item it = rs_decode_item(J, J.item_first + (item - J.item_begin));
+        const int n0 = it.nt * kTN, l0 = it.lt * TL;
+        const int64_t pb = (int64_t)it.s * J.chunk;
+        const int64_t pe = min(J.P, pb + (int64_t)J.chunk);
+        const int m = it.c / J.N, r = it.c % J.N;
+        const double *tx = J.ant + 3 * m;
+        const double *rx = J.ant + 3 * (J.M + r);
+
+        double2 acc[4][NJ];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) acc[i][j] = make_double2(0.0, 0.0);
+
+        for (int64_t p0 = pb; p0 < pe; p0 += kKP) {
+            if (tid < kKP) {
+                const int64_t p = p0 + tid;
+                if (p < pe) {
+                    rs_pixel_args a = rs_pixel(J, tx, rx, p);
+                    sPsi[tid] = a.psi_f;
+                    sB[tid] = a.b;
+                    sBeta[tid] = a.beta;
+                    sA[tid] = (double)a.a;
+                } else {
+                    sPsi[tid] = 0.0;
+                    sB[tid] = 0.0;
+                    sBeta[tid] = 0.0;
+                    sA[tid] = 0.0;
+                }
+            }
+            __syncthreads();
+            // fast-time phasors: F = exp(j 2pi phi), phi = wrap(psi_f + frac(b n))
+            for (int e = tid; e < kKP * kTN; e += 256) {
+                const int q = e / kTN, nn = e % kTN;
+                const double th = sB[q] * (double)(n0 + nn);
+                double phi = sPsi[q] + rs_frac(th);
+                phi = phi - __builtin_floor(phi + 0.5);
+                double sv, cv;
+                sincospi(2.0 * phi, &sv, &cv);
+                sF[q][nn] = make_double2(cv, sv);
+            }
+            // slow-time phasors: D = a exp(-j 2pi frac(beta l))
+            for (int e = tid; e < kKP * TL; e += 256) {
+                const int q = e / TL, ll = e % TL;
+                const double ph = rs_frac(sBeta[q] * (double)(l0 + ll));
+                double sv, cv;
+                sincospi(2.0 * ph, &sv, &cv);
+                const double a = sA[q];
+                sD[q][ll] = make_double2(a * cv, -(a * sv));
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int q = 0; q < kKP; ++q) {
+                double2 f[4], d[NJ];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) f[i] = sF[q][tn + 16 * i];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) d[j] = sD[q][tl + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        acc[i][j].x = __builtin_fma(f[i].x, d[j].x, acc[i][j].x);
+                        acc[i][j].x = __builtin_fma(-f[i].y, d[j].y, acc[i][j].x);
+                        acc[i][j].y = __builtin_fma(f[i].x, d[j].y, acc[i][j].y);
+                        acc[i][j].y = __builtin_fma(f[i].y, d[j].x, acc[i][j].y);
+                    }
+            }
+            __syncthreads();
+        }
+
+        double2 *out = reinterpret_cast<double2 *>(J.partial) +
+                       ((int64_t)it.s * (J.M * J.N) + it.c) * (int64_t)J.L * J.Ns;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = n0 + tn + 16 * i;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int l = l0 + tl + 16 * j;
+                if (n < J.Ns && l < J.L) out[(int64_t)l * J.Ns + n] = acc[i][j];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void rs_launch_plain(const rs_launch &L, int tl, int grid, hipStream_t st)
+{
+    if (tl == 64)
+        hipLaunchKernelGGL(k_plain_fp64<64>, dim3(grid), dim3(256), 0, st, L);
+    else
+        hipLaunchKernelGGL(k_plain_fp64<128>, dim3(grid), dim3(256), 0, st, L);
+}

@@ -1,0 +1,317 @@
+"""Python binding of librs (include/rs.h): argument marshalling only.
+
+Every step of the synthesis runs in the library's gfx950 kernels.  PyTorch
+supplies device memory (tensor data pointers) and HIP streams; nothing here
+computes any part of the cube.  If librs.so is missing this module raises on
+import: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librs.so")
+
+RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_UNSUPPORTED, RS_E_BUSY, RS_E_NOT_FOUND = range(7)
+RS_FORM_FP64_DIRECT, RS_FORM_MFMA_SPLIT16 = 0, 1
+RS_C64, RS_C128 = 0, 1
+RS_REQ_QUEUED, RS_REQ_RUNNING, RS_REQ_DONE, RS_REQ_FAILED, RS_REQ_CANCELLED = range(5)
+STATUS_NAMES = {0: "RS_OK", 1: "RS_E_INVALID", 2: "RS_E_NOMEM", 3: "RS_E_DEVICE",
+                4: "RS_E_UNSUPPORTED", 5: "RS_E_BUSY", 6: "RS_E_NOT_FOUND"}
+
+
+class RSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rs_radar(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("Ns", ctypes.c_int32),
+                ("L", ctypes.c_int32), ("fc", ctypes.c_double), ("mu", ctypes.c_double),
+                ("Fs", ctypes.c_double), ("Tb", ctypes.c_double), ("c0", ctypes.c_double),
+                ("tx_xyz", ctypes.POINTER(ctypes.c_double)),
+                ("rx_xyz", ctypes.POINTER(ctypes.c_double)),
+                ("carrier_phase", ctypes.c_int32)]
+
+
+class rs_pixels(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("amp", ctypes.c_void_p), ("vr", ctypes.c_void_p)]
+
+
+class rs_session_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t),
+                ("max_slots", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("slice_items", ctypes.c_int32)]
+
+
+class rs_timing(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class rs_session_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("done", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("queued_now", ctypes.c_int64), ("running_now", ctypes.c_int64),
+                ("footprint_now", ctypes.c_size_t), ("footprint_peak", ctypes.c_size_t),
+                ("terms_done", ctypes.c_double)]
+
+
+# Every symbol declared in include/rs.h: name -> (restype, argtypes)
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "rs_cube_plan": (ctypes.c_int, [ctypes.POINTER(rs_radar), ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int64, ctypes.POINTER(_VP)]),
+    "rs_plan_workspace_bytes": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "rs_plan_describe": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_char_p, ctypes.c_size_t]),
+    "rs_beat_synthesize": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP]),
+    "rs_beat_synthesize_ws": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP,
+                                             ctypes.c_size_t, _VP]),
+    "rs_beat_synthesize_batch": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), ctypes.c_int32,
+                                                _VP, _VP]),
+    "rs_plan_destroy": (None, [_VP]),
+    "rs_session_create": (ctypes.c_int, [ctypes.POINTER(rs_session_opts), ctypes.POINTER(_VP)]),
+    "rs_session_submit": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(rs_pixels), _VP,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "rs_session_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(rs_timing)]),
+    "rs_session_cancel": (ctypes.c_int, [_VP, ctypes.c_uint64]),
+    "rs_session_drain": (ctypes.c_int, [_VP]),
+    "rs_session_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(rs_session_stats)]),
+    "rs_session_destroy": (None, [_VP]),
+    "rs_session_inject_failure": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "rs_last_error": (ctypes.c_char_p, []),
+    "rs_version": (ctypes.c_char_p, []),
+}
+
+
+def _load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"librs.so not found at {path}: build it first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != RS_OK:
+        raise RSError(status, lib.rs_last_error().decode())
+
+
+def rs_version() -> str:
+    return lib.rs_version().decode()
+
+
+def rs_last_error() -> str:
+    return lib.rs_last_error().decode()
+
+
+# ----------------------------------------------------------------------------
+def _stream_handle(stream) -> int:
+    """HIP stream handle of a torch stream (None = torch's current stream)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class DevicePixels:
+    """Float32 structure-of-arrays pixels resident in device memory."""
+
+    def __init__(self, x, y, z, amp, vr):
+        self.x, self.y, self.z, self.amp, self.vr = x, y, z, amp, vr
+        self.P = int(x.numel())
+
+    @classmethod
+    def from_host(cls, px, device="cuda:0") -> "DevicePixels":
+        import torch
+        arrs = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+                for a in (px.x, px.y, px.z, px.amp, px.vr)]
+        return cls(*arrs)
+
+    def struct(self) -> rs_pixels:
+        if self.P == 0:
+            return rs_pixels(0, None, None, None, None, None)
+        for a in (self.x, self.y, self.z, self.amp, self.vr):
+            if a.numel() != self.P or not a.is_contiguous() or str(a.dtype) != "torch.float32":
+                raise ValueError("pixel arrays must be contiguous float32 of equal length")
+        return rs_pixels(self.P, _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.amp),
+                         _ptr(self.vr))
+
+
+class Plan:
+    """Owner of an rs_plan handle (rs_cube_plan / rs_plan_destroy)."""
+
+    def __init__(self, handle: int, radar, form: int, dtype: int, max_pixels: int):
+        self.handle = handle
+        self.radar = radar
+        self.form = form
+        self.dtype = dtype
+        self.max_pixels = max_pixels
+
+    @property
+    def cube_shape(self):
+        return (self.radar.M * self.radar.N, self.radar.L, self.radar.Ns)
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex128 if self.dtype == RS_C128 else torch.complex64
+
+    def describe(self, P: int) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        _check(lib.rs_plan_describe(self.handle, P, buf, 1024))
+        return buf.value.decode()
+
+    def workspace_bytes(self, P: int) -> int:
+        out = ctypes.c_size_t()
+        _check(lib.rs_plan_workspace_bytes(self.handle, P, ctypes.byref(out)))
+        return int(out.value)
+
+    def close(self):
+        if self.handle:
+            lib.rs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _radar_struct(radar):
+    tx = np.ascontiguousarray(radar.tx, dtype=np.float64).reshape(-1)
+    rx = np.ascontiguousarray(radar.rx, dtype=np.float64).reshape(-1)
+    if tx.size < 3 * max(radar.M, 0) or rx.size < 3 * max(radar.N, 0):
+        raise ValueError("antenna arrays must hold M x 3 and N x 3 positions")
+    st = rs_radar(int(radar.M), int(radar.N), int(radar.Ns), int(radar.L), float(radar.fc),
+                  float(radar.mu), float(radar.Fs), float(radar.Tb), float(radar.c0),
+                  tx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                  rx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                  int(radar.carrier_phase))
+    return st, (tx, rx)
+
+
+def rs_cube_plan(radar, form: int = RS_FORM_MFMA_SPLIT16, dtype: int = RS_C64,
+                 max_pixels: int = 1 << 20) -> Plan:
+    st, keep = _radar_struct(radar)
+    h = ctypes.c_void_p()
+    _check(lib.rs_cube_plan(ctypes.byref(st), form, dtype, max_pixels, ctypes.byref(h)))
+    return Plan(h.value, radar, form, dtype, max_pixels)
+
+
+def new_cube(plan: Plan, device="cuda:0", count: Optional[int] = None):
+    import torch
+    shape = plan.cube_shape if count is None else (count,) + plan.cube_shape
+    return torch.empty(shape, dtype=plan.torch_dtype, device=device)
+
+
+def rs_beat_synthesize(plan: Plan, pixels: DevicePixels, cube, stream=None):
+    ps = pixels.struct()
+    _check(lib.rs_beat_synthesize(plan.handle, ctypes.byref(ps), _ptr(cube),
+                                  _stream_handle(stream)))
+    return cube
+
+
+def rs_beat_synthesize_ws(plan: Plan, pixels: DevicePixels, cube, workspace, stream=None):
+    ps = pixels.struct()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib.rs_beat_synthesize_ws(plan.handle, ctypes.byref(ps), _ptr(cube),
+                                     _ptr(workspace) if nbytes else None, nbytes,
+                                     _stream_handle(stream)))
+    return cube
+
+
+def rs_beat_synthesize_batch(plan: Plan, frames: Sequence[DevicePixels], cubes, stream=None):
+    arr = (rs_pixels * max(1, len(frames)))()
+    for i, f in enumerate(frames):
+        arr[i] = f.struct()
+    _check(lib.rs_beat_synthesize_batch(plan.handle, arr, len(frames), _ptr(cubes),
+                                        _stream_handle(stream)))
+    return cubes
+
+
+# ----------------------------------------------------------------------------
+class Session:
+    """Owner of an rs_session handle (continuous-batching serving loop)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_slots: int = 16,
+                 queue_cap: int = 4096, slice_items: int = 0):
+        opts = rs_session_opts(device, hbm_budget, max_slots, queue_cap, slice_items)
+        h = ctypes.c_void_p()
+        _check(lib.rs_session_create(ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h.value
+        self._keep = {}
+
+    def submit(self, plan: Plan, pixels: DevicePixels, cube) -> int:
+        ps = pixels.struct()
+        t = ctypes.c_uint64()
+        _check(lib.rs_session_submit(self.handle, plan.handle, ctypes.byref(ps), _ptr(cube),
+                                     ctypes.byref(t)))
+        self._keep[t.value] = (plan, pixels, cube)
+        return int(t.value)
+
+    def try_submit(self, plan: Plan, pixels: DevicePixels, cube) -> Optional[int]:
+        """submit, or None when the queue is full (RS_E_BUSY)."""
+        try:
+            return self.submit(plan, pixels, cube)
+        except RSError as e:
+            if e.status == RS_E_BUSY:
+                return None
+            raise
+
+    def poll(self, ticket: int):
+        state = ctypes.c_int32()
+        tm = rs_timing()
+        _check(lib.rs_session_poll(self.handle, ticket, ctypes.byref(state), ctypes.byref(tm)))
+        if state.value in (RS_REQ_DONE, RS_REQ_FAILED, RS_REQ_CANCELLED):
+            self._keep.pop(ticket, None)
+        return state.value, (tm.t_submit_ns, tm.t_admit_ns, tm.t_done_ns)
+
+    def cancel(self, ticket: int):
+        _check(lib.rs_session_cancel(self.handle, ticket))
+
+    def drain(self):
+        _check(lib.rs_session_drain(self.handle))
+
+    def stats(self) -> dict:
+        st = rs_session_stats()
+        _check(lib.rs_session_stats_get(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in rs_session_stats._fields_}
+
+    def inject_failure(self, count: int = 1):
+        _check(lib.rs_session_inject_failure(self.handle, count))
+
+    def close(self):
+        if self.handle:
+            lib.rs_session_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rs_session_create(**kw) -> Session:
+    return Session(**kw)
