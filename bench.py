@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Throughput of per-pixel TDM-MIMO beat-cube synthesis on one MI355X.
+
+One step = one rs_beat_synthesize call (every stage of the path: pixel
+geometry, binary64 phase arguments, phasors, the complex contraction on the
+matrix cores, the split-K reduction) on the 256x256 room-plus-pedestrian
+frame: 65,536 pixels, 3 Tx x 4 Rx, Ns = 256, L = 128, complex64 output, split
+fp16 matrix-core form.  Inputs are resident in HBM before timing starts.
+
+Printed as one JSON line: terms/s (P*M*N*Ns*L per second), the roofline of
+the contraction kernel (HIP-event durations of that kernel during the timed
+steps), p50/p99 step latency, parity vs the CPU oracle on sampled entries,
+the plain binary64 form on the same frame, the 64-frame batched launch, the
+serving loop at a fixed request rate, and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "scatterer-sample terms/s (P*M*N*Ns*L/s) MFMA vs FP64-direct at stated err; p50/p99"
+PEAK_FP16 = 2.5e15     # dense fp16 matrix flop/s, MI355X
+PEAK_FP64 = 78.6e12    # fp64 vector flop/s, MI355X
+FLOP_MFMA = 24         # 3 split products x complex MAC (4 real MACs) x 2
+FLOP_PLAIN = 8         # one binary64 complex MAC
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline single-frame measurement")
+    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-rate", type=float, default=0.0,
+                    help="requests/s; 0 = 0.6 x the measured capacity")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def timed_steps(fn, steps, warmup):
+    """warmup untimed, then exactly `steps` timed calls bracketed by
+    synchronisation; per-step durations from events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(b) for a, b in evs]
+    return wall, per
+
+
+def parity_sampled(radar, px, cube_np, k=512, seed=11):
+    import oracle
+    rng = np.random.default_rng(seed)
+    C, L, Ns = radar.cube_shape()
+    c = rng.integers(0, C, k).astype(np.int32)
+    l = rng.integers(0, L, k).astype(np.int32)
+    n = rng.integers(0, Ns, k).astype(np.int32)
+    ref = oracle.entries(radar, px, c, l, n)
+    got = cube_np[c, l, n].astype(np.complex128)
+    d = got - ref
+    return {"relL2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "maxabs": float(np.max(np.abs(d)) / np.max(np.abs(ref))),
+            "entries": int(k)}
+
+
+def cpu_baseline(radar, px, seconds):
+    """The oracle's direct sum on a bounded sample of the same frame: a
+    number of seeded output entries, each a full sum over all pixels."""
+    import oracle
+    o = oracle.default()
+    cores = o.max_threads()
+    rng = np.random.default_rng(5)
+    C, L, Ns = radar.cube_shape()
+
+    def run(k):
+        c = rng.integers(0, C, k).astype(np.int32)
+        l = rng.integers(0, L, k).astype(np.int32)
+        n = rng.integers(0, Ns, k).astype(np.int32)
+        t = time.perf_counter()
+        o.entries(radar, px, c, l, n)
+        return time.perf_counter() - t
+
+    k0 = max(64, cores * 8)
+    dt = run(k0)
+    rate = k0 * px.P / dt
+    k = int(max(k0, min(200000, rate * seconds / px.P)))
+    dt = run(k)
+    return {"value": k * px.P / dt, "unit": "terms/s", "cores": cores, "kind": "oracle",
+            "sample": f"{k} seeded output entries of the headline frame, each summed over "
+                      f"all {px.P} pixels ({k * px.P:.3e} terms, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); multi-GPU runs are "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2307_09226_amd import rs, scenes
+
+    dev = "cuda:0"
+    radar, px = scenes.workload_frame()
+    terms = px.P * radar.C * radar.Ns * radar.L
+    dpx = rs.DevicePixels.from_host(px, dev)
+
+    # ---- headline: split-fp16 matrix-core form ---------------------------------
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
+    cube = rs.new_cube(plan, dev)
+    step = lambda: rs.rs_beat_synthesize(plan, dpx, cube)
+    timer = rs.KernelTimer(capacity=args.steps + args.warmup + 8)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    timer.read()
+    with timer:
+        wall, per = timed_steps(step, args.steps, 0)
+    kms = timer.read()
+    ms_step = wall * 1e3 / args.steps
+    value = terms / (wall / args.steps)
+    kavg = float(np.mean(kms)) if kms else float("nan")
+    achieved = FLOP_MFMA * terms / (kavg * 1e-3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "terms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16 hi/lo split, f32 accumulate (f64 phase arguments)", "data": "synthetic",
+        "config": {"workload": "room+pedestrian frame 256x256 px (65,536), 3 Tx x 4 Rx, "
+                               "Ns=256, L=128, Fs=10 MHz, Tb=3x40 us, complex64 cube",
+                   "form": "mfma_split16", "P": px.P, "M": radar.M, "N": radar.N,
+                   "Ns": radar.Ns, "L": radar.L, "terms_per_step": terms,
+                   "plan": json.loads(plan.describe(px.P))},
+        "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP16 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP16, "traffic": None,
+                     "kernel": "k_mfma_split16", "kernel_ms": kavg,
+                     "flop_per_term": FLOP_MFMA, "terms_per_launch": terms},
+    }
+    torch.cuda.synchronize()
+    out["parity"] = parity_sampled(radar, px, cube.cpu().numpy())
+
+    if not args.no_extras:
+        # ---- plain binary64 form on the same frame -------------------------------
+        pplan = rs.rs_cube_plan(radar, rs.RS_FORM_FP64_DIRECT, rs.RS_C64, max_pixels=px.P)
+        pcube = rs.new_cube(pplan, dev)
+        pstep = lambda: rs.rs_beat_synthesize(pplan, dpx, pcube)
+        with timer:
+            pwall, pper = timed_steps(pstep, 5, 1)
+        pk = timer.read()
+        pk_avg = float(np.mean(pk[1:])) if len(pk) > 1 else float("nan")
+        torch.cuda.synchronize()
+        out["plain_fp64"] = {
+            "terms_per_s": terms / (pwall / 5), "ms_per_step": pwall * 1e3 / 5,
+            "p50_ms": pct(pper, 50), "p99_ms": pct(pper, 99), "kernel_ms": pk_avg,
+            "roofline": {"bound": "fp64 vector", "achieved": FLOP_PLAIN * terms / (pk_avg * 1e-3) / 1e12,
+                         "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                         "frac": FLOP_PLAIN * terms / (pk_avg * 1e-3) / PEAK_FP64},
+            "parity": parity_sampled(radar, px, pcube.cpu().numpy()),
+        }
+        out["mfma_speedup_vs_plain"] = out["value"] / out["plain_fp64"]["terms_per_s"]
+        pplan.close()
+
+        # ---- 64 animation frames in one persistent launch -------------------------
+        frames = scenes.animation_frames(seed=3, nframes=64)
+        brad = scenes.radar_batch()
+        bplan = rs.rs_cube_plan(brad, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64,
+                                max_pixels=max(f.P for f in frames))
+        dfr = [rs.DevicePixels.from_host(f, dev) for f in frames]
+        cubes = rs.new_cube(bplan, dev, count=len(frames))
+        bterms = sum(f.P for f in frames) * brad.C * brad.Ns * brad.L
+        with timer:
+            bwall, bper = timed_steps(lambda: rs.rs_beat_synthesize_batch(bplan, dfr, cubes), 3, 1)
+        bk = timer.read()
+        torch.cuda.synchronize()
+        out["batch"] = {
+            "workload": "64 animation frames, 3 Tx x 4 Rx, Ns=256, L=64, one persistent launch",
+            "pixels_min": min(f.P for f in frames), "pixels_max": max(f.P for f in frames),
+            "pixels_total": sum(f.P for f in frames), "terms": bterms,
+            "ms": bwall * 1e3 / 3, "terms_per_s": bterms / (bwall / 3),
+            "kernel_ms": float(np.mean(bk[1:])) if len(bk) > 1 else None,
+            "mfma_frac": (FLOP_MFMA * bterms / (np.mean(bk[1:]) * 1e-3)) / PEAK_FP16 if len(bk) > 1 else None,
+            "parity_frame0": parity_sampled(brad, frames[0], cubes[0].cpu().numpy(), k=128),
+        }
+        del cubes, dfr
+        bplan.close()
+
+        # ---- serving loop at a fixed request rate -----------------------------------
+        if args.serving_requests > 0:
+            out["serving"] = serving(rs, scenes, dev, args)
+
+        # ---- CPU oracle on the host cores -------------------------------------------
+        out["cpu_baseline"] = cpu_baseline(radar, px, args.cpu_seconds)
+    timer.close()
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def serving(rs, scenes, dev, args):
+    """Poisson arrivals of mixed cube requests at a fixed rate; latency is
+    completion minus submission per request."""
+    import torch
+    pool_n = 48
+    pool = scenes.serving_requests(pool_n)
+    plans = {}
+    items = []
+    for q in pool:
+        key = (q.radar.M, q.radar.N, q.radar.Ns, q.radar.L)
+        if key not in plans:
+            plans[key] = rs.rs_cube_plan(q.radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64,
+                                         max_pixels=262144)
+        items.append((plans[key], rs.DevicePixels.from_host(q.pixels, dev), q.terms))
+    max_slots = 16
+    sess = rs.Session(hbm_budget=16 << 30, max_slots=max_slots, queue_cap=100000)
+    # cubes are reused round-robin; each request writes its own buffer
+    bufs = [rs.new_cube(p, dev) for p, _, _ in items]
+    torch.cuda.synchronize()
+
+    def run(n, rate, seed):
+        arr = scenes.poisson_arrivals(n, rate, seed=seed) if rate > 0 else np.zeros(n)
+        order = np.random.default_rng(seed).integers(0, len(items), n)
+        tickets = []
+        terms = 0.0
+        t0 = time.perf_counter()
+        for i in range(n):
+            while time.perf_counter() - t0 < arr[i]:
+                time.sleep(0.0002)
+            p, d, tm = items[order[i]]
+            tickets.append(sess.submit(p, d, bufs[order[i]]))
+            terms += tm
+        sess.drain()
+        wall = time.perf_counter() - t0
+        lat = []
+        for t in tickets:
+            st, (ts, ta, td) = sess.poll(t)
+            assert st == rs.RS_REQ_DONE, st
+            lat.append((td - ts) * 1e-6)
+        return wall, terms, lat
+
+    # capacity: everything submitted at once
+    warm_n = 64
+    wall, terms, _ = run(warm_n, 0.0, 1)
+    cap_rps = warm_n / wall
+    rate = args.serving_rate if args.serving_rate > 0 else 0.6 * cap_rps
+    n = args.serving_requests
+    wall, terms, lat = run(n, rate, 7)
+    st = sess.stats()
+    sess.close()
+    for p in plans.values():
+        p.close()
+    return {"workload": "Poisson arrivals of mixed requests (1x4, 3x4, 12x16 arrays; Ns 128/256/512; "
+                        "L 64/128/256; 4k-262k pixels), pool of 48 seeded requests",
+            "capacity_req_per_s": cap_rps, "rate_req_per_s": rate, "requests": n,
+            "throughput_req_per_s": n / wall, "terms_per_s": terms / wall,
+            "latency_p50_ms": pct(lat, 50), "latency_p99_ms": pct(lat, 99),
+            "launches": int(st["launches"]), "footprint_peak_bytes": int(st["footprint_peak"]),
+            "max_slots": max_slots}
+
+
+if __name__ == "__main__":
+    main()

@@ -204,6 +204,24 @@ void rs_session_destroy(rs_session *s);
  * affected). */
 rs_status rs_session_inject_failure(rs_session *s, int32_t count);
 
+/* --------------------------------------------------------- kernel timer -- */
+/* Per-launch timing of the main (contraction) kernel with HIP events, for
+ * profiling.  A timer attached to the calling thread records an event pair
+ * around every main-kernel launch made by rs_beat_synthesize* and
+ * rs_beat_synthesize_batch from that thread, on the launch's stream, until
+ * `capacity` launches are recorded.  Create and read on the plan's device. */
+typedef struct rs_kernel_timer rs_kernel_timer;
+
+/* Errors: RS_E_INVALID (capacity < 1), RS_E_NOMEM, RS_E_DEVICE. */
+rs_status rs_kernel_timer_create(int32_t capacity, rs_kernel_timer **out);
+/* Attach to / detach from the calling thread (NULL detaches). */
+rs_status rs_kernel_timer_attach(rs_kernel_timer *t);
+/* Wait for the recorded launches and copy up to `max` durations in
+ * milliseconds into ms (may be NULL); *count = launches recorded.  Resets the
+ * timer.  Errors: RS_E_INVALID, RS_E_DEVICE. */
+rs_status rs_kernel_timer_read(rs_kernel_timer *t, double *ms, int32_t max, int32_t *count);
+void rs_kernel_timer_destroy(rs_kernel_timer *t);
+
 /* ---------------------------------------------------------------- misc -- */
 const char *rs_last_error(void);
 const char *rs_version(void);

@@ -121,15 +121,80 @@ rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px)
     return RS_OK;
 }
 
+// ---------------------------------------------------------- kernel timer --
+
+struct rs_kernel_timer {
+    int device = 0;
+    int cap = 0, used = 0;
+    std::vector<hipEvent_t> ev;  // begin/end pairs
+};
+
+static thread_local rs_kernel_timer *tl_timer = nullptr;
+
+extern "C" rs_status rs_kernel_timer_create(int32_t capacity, rs_kernel_timer **out)
+{
+    if (!out || capacity < 1 || capacity > (1 << 20)) return rs_fail(RS_E_INVALID, "bad argument");
+    *out = nullptr;
+    rs_kernel_timer *t = new (std::nothrow) rs_kernel_timer();
+    if (!t) return rs_fail(RS_E_NOMEM, "host allocation failed");
+    (void)hipGetDevice(&t->device);
+    t->cap = capacity;
+    t->ev.resize(2 * (size_t)capacity, nullptr);
+    for (auto &e : t->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            rs_kernel_timer_destroy(t);
+            return rs_fail(RS_E_DEVICE, "hipEventCreate failed");
+        }
+    *out = t;
+    return RS_OK;
+}
+
+extern "C" rs_status rs_kernel_timer_attach(rs_kernel_timer *t)
+{
+    tl_timer = t;
+    return RS_OK;
+}
+
+extern "C" rs_status rs_kernel_timer_read(rs_kernel_timer *t, double *ms, int32_t max, int32_t *count)
+{
+    if (!t || !count || max < 0) return rs_fail(RS_E_INVALID, "bad argument");
+    for (int i = 0; i < t->used; ++i) {
+        float v = 0.f;
+        if (hipEventSynchronize(t->ev[2 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&v, t->ev[2 * i], t->ev[2 * i + 1]) != hipSuccess)
+            return rs_fail(RS_E_DEVICE, "event timing failed");
+        if (ms && i < max) ms[i] = v;
+    }
+    *count = t->used;
+    t->used = 0;
+    return RS_OK;
+}
+
+extern "C" void rs_kernel_timer_destroy(rs_kernel_timer *t)
+{
+    if (!t) return;
+    if (tl_timer == t) tl_timer = nullptr;
+    for (auto &e : t->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete t;
+}
+
 rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, int grid, hipStream_t st)
 {
     if (L.total <= 0) return RS_OK;
+    rs_kernel_timer *tm = tl_timer;
+    const bool timed = tm && tm->used < tm->cap;
+    if (timed) (void)hipEventRecord(tm->ev[2 * tm->used], st);
     if (pl->form == RS_FORM_FP64_DIRECT)
         rs_launch_plain(L, pl->tl, grid, st);
     else
         rs_launch_mfma(L, pl->wn, pl->tl, grid, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "main kernel launch: %s", hipGetErrorString(e));
+    if (timed) {
+        (void)hipEventRecord(tm->ev[2 * tm->used + 1], st);
+        tm->used++;
+    }
     return RS_OK;
 }
 

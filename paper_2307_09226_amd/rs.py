@@ -87,6 +87,11 @@ SIGNATURES = {
     "rs_session_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(rs_session_stats)]),
     "rs_session_destroy": (None, [_VP]),
     "rs_session_inject_failure": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "rs_kernel_timer_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP)]),
+    "rs_kernel_timer_attach": (ctypes.c_int, [_VP]),
+    "rs_kernel_timer_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "rs_kernel_timer_destroy": (None, [_VP]),
     "rs_last_error": (ctypes.c_char_p, []),
     "rs_version": (ctypes.c_char_p, []),
 }
@@ -315,3 +320,38 @@ class Session:
 
 def rs_session_create(**kw) -> Session:
     return Session(**kw)
+
+
+class KernelTimer:
+    """HIP-event durations of main-kernel launches made from this thread
+    (rs_kernel_timer_*)."""
+
+    def __init__(self, capacity: int = 4096):
+        h = ctypes.c_void_p()
+        _check(lib.rs_kernel_timer_create(capacity, ctypes.byref(h)))
+        self.handle = h.value
+        self.capacity = capacity
+
+    def __enter__(self):
+        _check(lib.rs_kernel_timer_attach(self.handle))
+        return self
+
+    def __exit__(self, *exc):
+        lib.rs_kernel_timer_attach(None)
+
+    def read(self) -> List[float]:
+        buf = (ctypes.c_double * self.capacity)()
+        n = ctypes.c_int32()
+        _check(lib.rs_kernel_timer_read(self.handle, buf, self.capacity, ctypes.byref(n)))
+        return [buf[i] for i in range(min(n.value, self.capacity))]
+
+    def close(self):
+        if self.handle:
+            lib.rs_kernel_timer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
