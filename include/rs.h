@@ -151,7 +151,8 @@ typedef struct {
     size_t hbm_budget;    /* bytes of session workspace (partial sums) in flight */
     int32_t max_slots;    /* requests admitted at once (>= 1)                    */
     int32_t queue_cap;    /* requests queued before submit returns RS_E_BUSY     */
-    int32_t slice_items;  /* work items per launch, 0 = automatic                */
+    int32_t slice_items;  /* per request and launch: work items x 256-pixel steps;
+                             0 = automatic (~2 ms of matrix work per launch)      */
 } rs_session_opts;
 
 typedef enum {

@@ -79,6 +79,18 @@ size_t rs_partial_bytes(const rs_plan *pl, int32_t S)
     return (b + 255) & ~(size_t)255;
 }
 
+size_t rs_workspace_bytes(const rs_plan *pl, int32_t S)
+{
+    size_t scale = pl->form == RS_FORM_MFMA_SPLIT16 ? (((size_t)S * 4 + 255) & ~(size_t)255) : 0;
+    return rs_partial_bytes(pl, S) + scale;
+}
+
+int32_t rs_steps_per_chunk(const rs_plan *pl, int32_t chunk)
+{
+    (void)pl;
+    return (chunk + 15) / 16;
+}
+
 rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *partial,
                    int32_t S, int32_t chunk)
 {
@@ -106,7 +118,20 @@ rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *par
     j.chunk = chunk;
     j.item_count = (int64_t)S * pl->C * pl->n_tiles * pl->l_tiles;
     j.dtype = pl->dtype == RS_C128 ? 1 : 0;
+    j.seg_begin = 0;
+    j.seg_end = 0x7fffffff;
+    j.scale = pl->form == RS_FORM_MFMA_SPLIT16 && partial
+                  ? reinterpret_cast<int32_t *>(static_cast<char *>(partial) + rs_partial_bytes(pl, S))
+                  : nullptr;
     return j;
+}
+
+rs_status rs_launch_scale_checked(const rs_launch &L, hipStream_t st)
+{
+    rs_launch_chunk_scale(L, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "chunk-scale launch: %s", hipGetErrorString(e));
+    return RS_OK;
 }
 
 rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px)
@@ -326,7 +351,7 @@ extern "C" rs_status rs_plan_workspace_bytes(const rs_plan *pl, int64_t P, size_
     int32_t S, chunk;
     rs_status s = rs_plan_chunking(pl, P, &S, &chunk);
     if (s != RS_OK) return s;
-    *bytes = rs_partial_bytes(pl, S);
+    *bytes = rs_workspace_bytes(pl, S);
     return RS_OK;
 }
 
@@ -360,7 +385,7 @@ extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, voi
     if (s != RS_OK) return s;
     int32_t S, chunk;
     if ((s = rs_plan_chunking(pl, px->P, &S, &chunk)) != RS_OK) return s;
-    const size_t need = rs_partial_bytes(pl, S);
+    const size_t need = rs_workspace_bytes(pl, S);
     if (need > 0 && (!ws || ws_bytes < need))
         return rs_fail(RS_E_INVALID, "workspace too small: need %zu bytes", need);
     if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 255))
@@ -373,6 +398,11 @@ extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, voi
     std::memset(&L, 0, sizeof L);
     L.inline_job = rs_make_job(pl, px, cube, ws, S, chunk);
     L.njobs = 1;
+    if (pl->form == RS_FORM_MFMA_SPLIT16 && S > 0) {
+        rs_launch Sc = L;
+        Sc.total = S;
+        if ((s = rs_launch_scale_checked(Sc, st)) != RS_OK) return s;
+    }
     L.total = L.inline_job.item_count;
     if ((s = rs_launch_main(pl, L, (int)L.total, st)) != RS_OK) return s;
     rs_launch R = L;
@@ -421,22 +451,32 @@ extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *fram
     std::vector<rs_job> jobs(nframes);
     const size_t head = 256 + (((size_t)nframes * sizeof(rs_job) + 255) & ~(size_t)255);
     size_t off = head;
-    int64_t items = 0, outs = 0;
+    int64_t items = 0, outs = 0, chunks = 0;
+    std::vector<size_t> offs(nframes);
     for (int f = 0; f < nframes; ++f) {
         int32_t S, chunk;
         if ((s = rs_plan_chunking(pl, frames[f].P, &S, &chunk)) != RS_OK) return s;
-        jobs[f] = rs_make_job(pl, &frames[f], static_cast<char *>(cubes) + f * cube_bytes,
-                              reinterpret_cast<void *>(off), S, chunk);
+        offs[f] = off;
+        jobs[f] = rs_make_job(pl, &frames[f], static_cast<char *>(cubes) + f * cube_bytes, nullptr,
+                              S, chunk);
         jobs[f].item_begin = items;
         jobs[f].out_begin = outs;
+        jobs[f].chunk_begin = chunks;
         items += jobs[f].item_count;
         outs += (int64_t)pl->C * pl->L * pl->Ns;
-        off += rs_partial_bytes(pl, S);
+        chunks += S;
+        off += rs_workspace_bytes(pl, S);
     }
     char *ws = nullptr;
     if (hipMallocAsync(reinterpret_cast<void **>(&ws), off, st) != hipSuccess)
         return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", off);
-    for (auto &j : jobs) j.partial = ws + reinterpret_cast<uintptr_t>(j.partial);
+    for (int f = 0; f < nframes; ++f) {
+        rs_job j = rs_make_job(pl, &frames[f], jobs[f].cube, ws + offs[f], jobs[f].S, jobs[f].chunk);
+        j.item_begin = jobs[f].item_begin;
+        j.out_begin = jobs[f].out_begin;
+        j.chunk_begin = jobs[f].chunk_begin;
+        jobs[f] = j;
+    }
     rs_job *djobs = reinterpret_cast<rs_job *>(ws + 256);
     // The host job table is pageable: the runtime stages it before returning.
     hipError_t e = hipMemcpyAsync(djobs, jobs.data(), jobs.size() * sizeof(rs_job),
@@ -452,7 +492,13 @@ extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *fram
     L.total = items;
     L.counter = reinterpret_cast<int *>(ws);
     s = RS_OK;
-    if (items > 0) {
+    if (pl->form == RS_FORM_MFMA_SPLIT16 && chunks > 0) {
+        rs_launch Sc = L;
+        Sc.counter = nullptr;
+        Sc.total = chunks;
+        s = rs_launch_scale_checked(Sc, st);
+    }
+    if (s == RS_OK && items > 0) {
         rs_launch_zero_int(L.counter, 1, st);
         int64_t grid = (int64_t)pl->ncu * pl->occupancy;
         if (grid > items) grid = items;

@@ -25,6 +25,9 @@ rs_status rs_fail(rs_status s, const char *fmt, ...);
 void rs_choose_tiles(rs_plan *pl);
 rs_status rs_plan_chunking(const rs_plan *pl, int64_t P, int32_t *S, int32_t *chunk);
 size_t rs_partial_bytes(const rs_plan *pl, int32_t S);
+size_t rs_workspace_bytes(const rs_plan *pl, int32_t S);   // partials + chunk scales
+int32_t rs_steps_per_chunk(const rs_plan *pl, int32_t chunk);
+rs_status rs_launch_scale_checked(const rs_launch &L, hipStream_t st);
 rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *partial,
                    int32_t S, int32_t chunk);
 rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px);

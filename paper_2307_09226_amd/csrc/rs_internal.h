@@ -20,6 +20,9 @@ struct rs_job {
     int64_t item_first;        // first job-local work item covered by this launch
     int64_t item_count;        // job-local work items covered by this launch
     int64_t out_begin;         // first launch-global output entry (reduce launches)
+    int64_t chunk_begin;       // first launch-global pixel chunk (chunk-scale launches)
+    int32_t *scale;            // [S] per-chunk strength exponent shift (matrix-core form)
+    int32_t seg_begin, seg_end;  // 16-pixel steps of every chunk covered by this launch
     int32_t dtype;             // 0 = complex64, 1 = complex128
     int32_t pad_;
 };
@@ -42,16 +45,19 @@ __device__ __forceinline__ const rs_job &rs_job_of(const rs_launch &L, int j)
     return L.jobs ? L.jobs[j] : L.inline_job;
 }
 
-// Largest j with begin(j) <= g (jobs sorted by begin); begin = item_begin or
-// out_begin.
-template <bool OUT>
+enum { RS_BY_ITEM = 0, RS_BY_OUT = 1, RS_BY_CHUNK = 2 };
+
+// Largest j with begin(j) <= g (jobs sorted by begin); begin = item_begin,
+// out_begin or chunk_begin.
+template <int BY>
 __device__ __forceinline__ int rs_find_job(const rs_launch &L, int64_t g)
 {
     if (!L.jobs) return 0;
     int lo = 0, hi = L.njobs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        int64_t b = OUT ? L.jobs[mid].out_begin : L.jobs[mid].item_begin;
+        const rs_job &J = L.jobs[mid];
+        int64_t b = BY == RS_BY_ITEM ? J.item_begin : (BY == RS_BY_OUT ? J.out_begin : J.chunk_begin);
         if (b <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
@@ -79,4 +85,5 @@ __device__ __forceinline__ rs_item rs_decode_item(const rs_job &J, int64_t local
 void rs_launch_plain(const rs_launch &L, int tl, int grid, hipStream_t st);
 void rs_launch_mfma(const rs_launch &L, int wn, int tl, int grid, hipStream_t st);
 void rs_launch_reduce(const rs_launch &L, int form, hipStream_t st);
+void rs_launch_chunk_scale(const rs_launch &L, hipStream_t st);
 void rs_launch_zero_int(int *p, int n, hipStream_t st);

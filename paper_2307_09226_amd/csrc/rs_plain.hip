@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
         const int64_t item = rs_next_item(Lc, &s_item, first);
         first = false;
         if (item < 0) break;
-        const int jidx = rs_find_job<false>(Lc, item);
+        const int jidx = rs_find_job<RS_BY_ITEM>(Lc, item);
         const rs_job &J = rs_job_of(Lc, jidx);
         const rs_item it = rs_decode_item(J, J.item_first + (item - J.item_begin));
         const int n0 = it.nt * kTN, l0 = it.lt * TL;

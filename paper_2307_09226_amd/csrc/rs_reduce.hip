@@ -10,7 +10,7 @@ __global__ __launch_bounds__(256) void k_reduce(rs_launch Lc)
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= Lc.total) return;
-    const int jidx = rs_find_job<true>(Lc, g);
+    const int jidx = rs_find_job<RS_BY_OUT>(Lc, g);
     const rs_job &J = rs_job_of(Lc, jidx);
     const int64_t idx = g - J.out_begin;
     const int64_t cln = (int64_t)(J.M * J.N) * J.L * J.Ns;

@@ -46,12 +46,15 @@ struct request {
     int32_t state = RS_REQ_QUEUED;
     rs_timing tm{};
     int32_t S = 0, chunk = 0;
-    int64_t items = 0, cursor = 0;
+    int64_t items = 0;
+    int32_t steps = 0;        // 16-pixel steps of a full chunk
+    int32_t cursor = 0;       // next step segment to enqueue
+    bool scaled = false;      // per-chunk strength scales enqueued
     size_t footprint = 0, arena_off = 0;
     bool failed = false;
     bool issued_all = false;  // every work item (and the reduction) enqueued
     double terms = 0;
-    double item_terms = 0;
+    double step_terms = 0;    // terms of one 16-pixel step of one work item
 };
 
 // First-fit allocator over [0, size) in 256-byte units.
@@ -174,36 +177,139 @@ void admit(rs_session *s)
 
 struct slice_part {
     request *r;
-    int64_t first, count;
+    int32_t seg_begin, seg_end;  // 16-pixel steps of every chunk
+    bool scale;                  // enqueue the request's chunk scales first
 };
 
-// Work items of every admitted request for one slice (caller holds mu).
+// Work of every admitted request for one slice (caller holds mu): all work
+// items of a request over a segment of steps sized to an equal share of the
+// slice (segments start at 256-pixel boundaries).
 std::vector<slice_part> build_slice(rs_session *s, std::vector<request *> &completing)
 {
+    constexpr int kBlockSteps = 16;
     std::vector<slice_part> parts;
     std::vector<request *> pend;
     for (request *r : s->active)
         if (!r->issued_all) pend.push_back(r);
     if (pend.empty()) return parts;
-    const double target_terms = 1.2e11;  // ~2 ms of matrix-core work
+    const double target_terms = s->slice_items > 0 ? 0.0 : 1.2e11;  // ~2 ms of matrix-core work
     const double share = target_terms / pend.size();
-    const int64_t min_items = std::max<int64_t>(1, (s->ncu + pend.size() - 1) / pend.size());
-    int64_t total = 0;
     for (request *r : pend) {
-        int64_t q = (int64_t)(share / std::max(1.0, r->item_terms));
-        q = std::max(q, min_items);
-        if (s->slice_items > 0)
-            q = std::min<int64_t>(q, std::max<int64_t>(1, s->slice_items / (int64_t)pend.size()));
-        q = std::min(q, r->items - r->cursor);
-        if (q > 0) parts.push_back({r, r->cursor, q});
-        r->cursor += q;
-        total += q;
-        if (r->cursor >= r->items) {  // includes P = 0 (no items, zero cube)
+        const int32_t left = r->steps - r->cursor;
+        int64_t seg;
+        if (s->slice_items > 0) {
+            seg = (int64_t)s->slice_items * kBlockSteps / std::max<int64_t>(1, r->items);
+        } else {
+            const double per_step = std::max(1.0, r->step_terms * (double)r->items);
+            seg = (int64_t)(share / per_step);
+        }
+        seg = std::max<int64_t>(kBlockSteps, (seg / kBlockSteps) * kBlockSteps);
+        if (seg >= left) seg = left;
+        slice_part p{r, r->cursor, (int32_t)(r->cursor + seg), !r->scaled};
+        r->scaled = true;
+        r->cursor += (int32_t)seg;
+        if (r->items > 0 && seg > 0) parts.push_back(p);
+        if (r->cursor >= r->steps) {  // includes P = 0 (no items, zero cube)
             r->issued_all = true;
             completing.push_back(r);
         }
     }
     return parts;
+}
+
+// Enqueue one slice on the session stream: chunk scales of newly started
+// requests, one persistent launch per tile shape, reductions of the requests
+// completed by the slice.  One host-to-device copy carries all job tables.
+hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_part> &parts,
+                         const std::vector<request *> &completing)
+{
+    int nj = 0;
+    // chunk-scale jobs
+    const int js = nj;
+    int64_t chunks = 0;
+    for (const auto &p : parts) {
+        if (!p.scale) continue;
+        rs_job j = rs_make_job(p.r->plan, &p.r->px, p.r->cube, s->arena + p.r->arena_off, p.r->S,
+                               p.r->chunk);
+        j.chunk_begin = chunks;
+        chunks += p.r->S;
+        rg.h_jobs[nj++] = j;
+    }
+    const int nscale = nj - js;
+    // main jobs grouped by tile shape
+    struct group {
+        int wn, tl, j0, n;
+        int64_t items;
+        const rs_plan *pl;
+    };
+    std::vector<group> groups;
+    for (const auto &p : parts) {
+        bool found = false;
+        for (auto &g : groups)
+            if (g.wn == p.r->plan->wn && g.tl == p.r->plan->tl) found = true;
+        if (!found) groups.push_back(group{p.r->plan->wn, p.r->plan->tl, 0, 0, 0, p.r->plan});
+    }
+    for (auto &g : groups) {
+        g.j0 = nj;
+        for (const auto &p : parts) {
+            if (p.r->plan->wn != g.wn || p.r->plan->tl != g.tl) continue;
+            rs_job j = rs_make_job(p.r->plan, &p.r->px, p.r->cube, s->arena + p.r->arena_off,
+                                   p.r->S, p.r->chunk);
+            j.item_begin = g.items;
+            j.item_first = 0;
+            j.item_count = p.r->items;
+            j.seg_begin = p.seg_begin;
+            j.seg_end = p.seg_end;
+            g.items += p.r->items;
+            rg.h_jobs[nj++] = j;
+        }
+        g.n = nj - g.j0;
+    }
+    // reduction jobs
+    const int jr = nj;
+    int64_t outs = 0;
+    for (request *r : completing) {
+        rs_job j = rs_make_job(r->plan, &r->px, r->cube, s->arena + r->arena_off, r->S, r->chunk);
+        j.out_begin = outs;
+        outs += (int64_t)r->plan->C * r->plan->L * r->plan->Ns;
+        rg.h_jobs[nj++] = j;
+    }
+    const int nred = nj - jr;
+    if (nj == 0) return hipSuccess;
+    hipError_t err = hipMemcpyAsync(rg.d_jobs, rg.h_jobs, (size_t)nj * sizeof(rs_job),
+                                    hipMemcpyHostToDevice, s->stream);
+    if (err != hipSuccess) return err;
+    if (nscale > 0) {
+        rs_launch Sc;
+        std::memset(&Sc, 0, sizeof Sc);
+        Sc.jobs = rg.d_jobs + js;
+        Sc.njobs = nscale;
+        Sc.total = chunks;
+        if (rs_launch_scale_checked(Sc, s->stream) != RS_OK) return hipErrorLaunchFailure;
+    }
+    int launch = 0;
+    for (auto &g : groups) {
+        if (g.items <= 0) continue;
+        rs_launch L;
+        std::memset(&L, 0, sizeof L);
+        L.jobs = rg.d_jobs + g.j0;
+        L.njobs = g.n;
+        L.total = g.items;
+        L.counter = rg.d_counter + launch++;
+        rs_launch_zero_int(L.counter, 1, s->stream);
+        const int64_t grid = std::min<int64_t>(g.items, (int64_t)s->ncu * g.pl->occupancy);
+        if (rs_launch_main(g.pl, L, (int)grid, s->stream) != RS_OK) return hipErrorLaunchFailure;
+    }
+    if (nred > 0) {
+        rs_launch R;
+        std::memset(&R, 0, sizeof R);
+        R.jobs = rg.d_jobs + jr;
+        R.njobs = nred;
+        R.total = outs;
+        if (rs_launch_reduce_checked(completing[0]->plan, R, s->stream) != RS_OK)
+            return hipErrorLaunchFailure;
+    }
+    return hipSuccess;
 }
 
 void worker_main(rs_session *s)
@@ -239,15 +345,6 @@ void worker_main(rs_session *s)
         if (s->inject_fail > 0) {
             s->inject_fail--;
             fail = true;
-            for (auto &p : parts) {
-                p.r->failed = true;
-                if (!p.r->issued_all) {
-                    p.r->cursor = p.r->items;
-                    p.r->issued_all = true;
-                    completing.push_back(p.r);
-                }
-            }
-            for (request *r : completing) r->failed = true;
         }
         const int slot = s->ring_next;
         s->ring_next = (s->ring_next + 1) % kRing;
@@ -255,87 +352,24 @@ void worker_main(rs_session *s)
         s->st.launches++;
         lk.unlock();
 
-        // ---- enqueue the slice (no lock held) --------------------------------
         ring_slot &rg = s->ring[slot];
-        int nj = 0;
-        hipError_t err = hipSuccess;
-        if (!fail) {
-            // group parts by tile shape: one persistent launch per shape
-            std::vector<std::pair<int, int>> shapes;
-            for (auto &p : parts) {
-                std::pair<int, int> k(p.r->plan->wn, p.r->plan->tl);
-                if (std::find(shapes.begin(), shapes.end(), k) == shapes.end()) shapes.push_back(k);
-            }
-            int launch = 0;
-            for (auto &shp : shapes) {
-                const int j0 = nj;
-                int64_t items = 0;
-                for (auto &p : parts) {
-                    if (p.r->plan->wn != shp.first || p.r->plan->tl != shp.second) continue;
-                    rs_job j = rs_make_job(p.r->plan, &p.r->px, p.r->cube, s->arena + p.r->arena_off,
-                                           p.r->S, p.r->chunk);
-                    j.item_begin = items;
-                    j.item_first = p.first;
-                    j.item_count = p.count;
-                    items += p.count;
-                    rg.h_jobs[nj++] = j;
-                }
-                rs_launch L;
-                std::memset(&L, 0, sizeof L);
-                L.jobs = rg.d_jobs + j0;
-                L.njobs = nj - j0;
-                L.total = items;
-                L.counter = rg.d_counter + launch;
-                const rs_plan *pl = parts[0].r->plan;
-                for (auto &p : parts)
-                    if (p.r->plan->wn == shp.first && p.r->plan->tl == shp.second) pl = p.r->plan;
-                err = hipMemcpyAsync(rg.d_jobs + j0, rg.h_jobs + j0, (size_t)(nj - j0) * sizeof(rs_job),
-                                     hipMemcpyHostToDevice, s->stream);
-                if (err != hipSuccess) break;
-                rs_launch_zero_int(L.counter, 1, s->stream);
-                int64_t grid = std::min<int64_t>(items, (int64_t)s->ncu * pl->occupancy);
-                if (rs_launch_main(pl, L, (int)grid, s->stream) != RS_OK) {
-                    err = hipErrorLaunchFailure;
-                    break;
-                }
-                launch++;
-            }
-            // reduction of the requests completed by this slice
-            if (err == hipSuccess && !completing.empty()) {
-                const int j0 = nj;
-                int64_t outs = 0;
-                for (request *r : completing) {
-                    rs_job j = rs_make_job(r->plan, &r->px, r->cube, s->arena + r->arena_off, r->S,
-                                           r->chunk);
-                    j.out_begin = outs;
-                    outs += (int64_t)r->plan->C * r->plan->L * r->plan->Ns;
-                    rg.h_jobs[nj++] = j;
-                }
-                err = hipMemcpyAsync(rg.d_jobs + j0, rg.h_jobs + j0, (size_t)(nj - j0) * sizeof(rs_job),
-                                     hipMemcpyHostToDevice, s->stream);
-                if (err == hipSuccess) {
-                    rs_launch R;
-                    std::memset(&R, 0, sizeof R);
-                    R.jobs = rg.d_jobs + j0;
-                    R.njobs = nj - j0;
-                    R.total = outs;
-                    if (rs_launch_reduce_checked(completing[0]->plan, R, s->stream) != RS_OK)
-                        err = hipErrorLaunchFailure;
-                }
-            }
-        }
+        hipError_t err = fail ? hipErrorLaunchFailure : enqueue_slice(s, rg, parts, completing);
+        (void)hipEventRecord(rg.done, s->stream);
+
+        lk.lock();
         if (err != hipSuccess) {
+            // every request with work in this slice fails; it retires with
+            // this slice (no further work of it is enqueued)
             for (auto &p : parts) {
                 p.r->failed = true;
                 if (!p.r->issued_all) {
-                    completing.push_back(p.r);
-                    p.r->cursor = p.r->items;
                     p.r->issued_all = true;
+                    p.r->cursor = p.r->steps;
+                    completing.push_back(p.r);
                 }
             }
+            for (request *r : completing) r->failed = true;
         }
-        (void)hipEventRecord(rg.done, s->stream);
-        lk.lock();
         fly.push_back(inflight{slot, completing});
     }
 }
@@ -430,9 +464,10 @@ extern "C" rs_status rs_session_submit(rs_session *s, const rs_plan *pl, const r
     r->cube = cube;
     if ((st = rs_plan_chunking(pl, px->P, &r->S, &r->chunk)) != RS_OK) return st;
     r->items = (int64_t)r->S * pl->C * pl->n_tiles * pl->l_tiles;
-    r->footprint = rs_partial_bytes(pl, r->S);
+    r->steps = r->S > 0 ? rs_steps_per_chunk(pl, r->chunk) : 0;
+    r->footprint = rs_workspace_bytes(pl, r->S);
     r->terms = (double)px->P * pl->C * pl->L * pl->Ns;
-    r->item_terms = (double)r->chunk * pl->tn * pl->tl;
+    r->step_terms = 16.0 * pl->tn * pl->tl;
     if (r->footprint > s->budget)
         return rs_fail(RS_E_INVALID, "request needs %zu bytes of workspace, session budget is %zu",
                        r->footprint, s->budget);
