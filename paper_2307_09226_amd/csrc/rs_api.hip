@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -213,7 +214,7 @@ rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, int grid, hipStr
     if (pl->form == RS_FORM_FP64_DIRECT)
         rs_launch_plain(L, pl->tl, grid, st);
     else
-        rs_launch_mfma(L, pl->wn, pl->tl, grid, st);
+        rs_launch_mfma(L, pl->wn, pl->tl, pl->nw, grid, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "main kernel launch: %s", hipGetErrorString(e));
     if (timed) {
@@ -319,13 +320,34 @@ void rs_choose_tiles(rs_plan *pl)
         pl->min_chunk = 256;
         pl->occupancy = 2;
     } else {
-        pl->tl = pl->L <= 64 ? 64 : 128;
-        const int max_wn = pl->tl == 64 ? 128 : 64;  // 256 fp32 accumulators per lane
-        int need = (pl->Ns + 3) / 4;                 // rows per wave to cover Ns
-        int wn = 32;
-        while (wn < need && wn < max_wn) wn *= 2;
+        // Matrix-core tiles: TL columns (l), NW waves of WN rows (n).
+        //   L > 64: 128 columns; 8 waves x 32 rows (two waves per SIMD) when
+        //           Ns > 128, else 4 waves x 32 rows
+        //   L <= 64: 64 columns; 4 waves x 64 rows (Ns > 128) or x 32 rows
+        int wn, tl, nw;
+        if (pl->L > 64) {
+            tl = 128;
+            wn = 32;
+            nw = pl->Ns > 128 ? 8 : 4;
+        } else {
+            tl = 64;
+            nw = 4;
+            wn = pl->Ns > 128 ? 64 : 32;
+        }
+        // tuning override "WNxTLxNW", e.g. RS_MFMA_TILE=64x128x4
+        if (const char *ov = std::getenv("RS_MFMA_TILE")) {
+            int a = 0, b = 0, c = 4;
+            const int k = std::sscanf(ov, "%dx%dx%d", &a, &b, &c);
+            if (k >= 2 && rs_mfma_shape_supported(a, b, c)) {
+                wn = a;
+                tl = b;
+                nw = c;
+            }
+        }
         pl->wn = wn;
-        pl->tn = 4 * wn;
+        pl->tl = tl;
+        pl->nw = nw;
+        pl->tn = nw * wn;
         pl->items_target = pl->ncu;
         pl->min_chunk = 1024;
         pl->occupancy = 1;
@@ -365,11 +387,11 @@ extern "C" rs_status rs_plan_describe(const rs_plan *pl, int64_t P, char *buf, s
     if (len == 0) return RS_OK;
     snprintf(buf, len,
              "{\"form\": \"%s\", \"dtype\": \"%s\", \"C\": %d, \"Ns\": %d, \"L\": %d, "
-             "\"tile_n\": %d, \"tile_l\": %d, \"wave_rows\": %d, \"n_tiles\": %d, \"l_tiles\": %d, "
+             "\"tile_n\": %d, \"tile_l\": %d, \"wave_rows\": %d, \"waves\": %d, \"n_tiles\": %d, \"l_tiles\": %d, "
              "\"chunks\": %d, \"chunk_pixels\": %d, \"items\": %lld, \"cus\": %d}",
              pl->form == RS_FORM_FP64_DIRECT ? "fp64_direct" : "mfma_split16",
              pl->dtype == RS_C128 ? "complex128" : "complex64", pl->C, pl->Ns, pl->L, pl->tn,
-             pl->tl, pl->wn, pl->n_tiles, pl->l_tiles, S, chunk,
+             pl->tl, pl->wn, pl->form == RS_FORM_FP64_DIRECT ? 4 : pl->nw, pl->n_tiles, pl->l_tiles, S, chunk,
              (long long)S * pl->C * pl->n_tiles * pl->l_tiles, pl->ncu);
     return RS_OK;
 }

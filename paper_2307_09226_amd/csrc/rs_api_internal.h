@@ -15,6 +15,7 @@ struct rs_plan {
     int64_t max_pixels = 0;
     // tile configuration
     int tn = 0, tl = 0, wn = 0;     // tile rows (n), tile columns (l), rows per wave (MFMA)
+    int nw = 4;                     // waves per workgroup (MFMA)
     int n_tiles = 0, l_tiles = 0;
     int64_t items_target = 0;       // work items aimed at for one cube
     int min_chunk = 0;              // smallest pixel chunk

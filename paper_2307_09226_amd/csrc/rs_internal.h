@@ -83,7 +83,8 @@ __device__ __forceinline__ rs_item rs_decode_item(const rs_job &J, int64_t local
 
 // Kernel entry points (defined in the .hip files, launched by rs_api.hip).
 void rs_launch_plain(const rs_launch &L, int tl, int grid, hipStream_t st);
-void rs_launch_mfma(const rs_launch &L, int wn, int tl, int grid, hipStream_t st);
+void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, int grid, hipStream_t st);
+bool rs_mfma_shape_supported(int wn, int tl, int nw);
 void rs_launch_reduce(const rs_launch &L, int form, hipStream_t st);
 void rs_launch_chunk_scale(const rs_launch &L, hipStream_t st);
 void rs_launch_zero_int(int *p, int n, hipStream_t st);

@@ -15,14 +15,16 @@
 // and hi*hi + hi*lo + lo*hi are accumulated in fp32 by the matrix cores
 // (12 real MACs = 24 flop per term).
 //
-// Tiling (workgroup = 4 waves, one per SIMD):
-//   item  = (channel, n tile of 4*WN rows, l tile of TL columns, pixel chunk)
+// Tiling (workgroup = NW waves, NW/4 per SIMD):
+//   item  = (channel, n tile of NW*WN rows, l tile of TL columns, pixel chunk)
 //   wave  = WN rows x TL complex columns; WN/32 x 2TL/32 accumulator blocks
 //   F     = A operand, evaluated by each lane for exactly the rows and pixels
 //           it feeds to the matrix core (registers only, double-buffered so
 //           the next step's phasors are computed while the matrix cores run)
 //   D     = B operand, evaluated once per workgroup per 16-pixel step into
 //           double-buffered LDS (both column arrangements, hi and lo)
+// With two waves per SIMD (NW = 8) the hardware interleaves one wave's
+// matrix instructions with the other's phasor arithmetic.
 // Phasor cost: per pixel and lane one binary64-reduced phasor; the other rows
 // of the lane follow by binary32 rotation with exp(j2pi frac(32 b)), and the
 // slow-time phasors of a thread by rotation with exp(j2pi frac(16 beta)) --
@@ -40,7 +42,9 @@
 // how a chunk is split into segments.
 #include "rs_device.h"
 
+#include <cstdlib>
 #include <mutex>
+#include <type_traits>
 
 namespace {
 
@@ -59,36 +63,53 @@ struct __align__(16) pix_par {
     double b;             // R Kb, cycles per fast-time sample
     double beta;          // v Kd, cycles per block
     float e32x, e32y;     // exp(j2pi frac(32 b)): rotation by 32 rows
-    float s16x, s16y;     // exp(j2pi frac(16 beta)): rotation by 16 blocks
+    float srx, sry;       // exp(j2pi frac(LQ beta)): rotation by LQ blocks
     float a;              // scaled strength
     float pad_;
 };
 
-template <int WN, int TL>
-struct mfma_smem {
-    static constexpr int NCOL = 2 * TL;
-    char d[2][2][NCOL * kCS];   // [buffer][hi, lo][column][pixel-in-step][slot]
-    pix_par par[2][kPB];
-    int64_t item;
-};
-
-__device__ __forceinline__ unsigned pack2(_Float16 a, _Float16 b)
-{
-    half2v v = {a, b};
-    return __builtin_bit_cast(unsigned, v);
-}
-
 __device__ __forceinline__ float frac32(double v) { return (float)rs_frac(v); }
 
-template <int WN, int TL>
-__global__ __launch_bounds__(256, 1) void k_mfma_split16(rs_launch Lc)
+// hi = rne16(x) for a pair, packed in one register (v_cvt_pk_f16_f32)
+__device__ __forceinline__ half2v hi2(float x, float y) { return half2v{(_Float16)x, (_Float16)y}; }
+
+// lo = rne16(x - hi): x - hi is exact in fp32, so the mixed-precision
+// multiply-add -hi * 1 + x rounded once to fp16 gives it, one instruction per
+// component (v_fma_mixlo_f16 writes bits 15:0, v_fma_mixhi_f16 bits 31:16;
+// op_sel_hi marks the fp16 source, op_sel picks its half).
+__device__ __forceinline__ half2v lo2(float x, float y, half2v h)
 {
+    const unsigned hb = __builtin_bit_cast(unsigned, h);
+    unsigned r;
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hb), "v"(x));
+    asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(r) : "v"(hb), "v"(y));
+    return __builtin_bit_cast(half2v, r);
+}
+
+__device__ __forceinline__ unsigned bits(half2v v) { return __builtin_bit_cast(unsigned, v); }
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef std::integral_constant<int, 0> buf0_t;
+typedef std::integral_constant<int, 1> buf1_t;
+
+template <int WN, int TL, int NW, bool PHASE>
+__global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
+{
+    constexpr int NT = 64 * NW;          // threads per workgroup
     constexpr int RB = WN / 32;          // 32-row blocks per wave
     constexpr int CB = 2 * TL / 32;      // 32-column blocks (re / im alternate)
-    constexpr int TN = 4 * WN;
-    constexpr int DPT = kKP * TL / 256;  // D phasors per thread per step
-    extern __shared__ __align__(16) char smem_raw[];
-    mfma_smem<WN, TL> &sm = *reinterpret_cast<mfma_smem<WN, TL> *>(smem_raw);
+    constexpr int TN = NW * WN;          // tile rows
+    constexpr int LQ = NT / 16;          // D threads per pixel (blocks l = lq + LQ k)
+    constexpr int DPT = TL / LQ;         // D phasors per thread per step
+    static_assert(LQ == 16 || LQ == 32, "D column mapping assumes 16 or 32 threads per pixel");
+    static_assert(DPT >= 1 && DPT * LQ == TL, "TL must be a multiple of the D thread count");
+    // Separate LDS objects for the two D buffers: the compiler then knows
+    // that the next step's D stores never alias the operands being read.
+    constexpr int DBYTES = 2 * TL * kCS;
+    __shared__ __align__(16) char sD0[2][DBYTES];  // [hi, lo]
+    __shared__ __align__(16) char sD1[2][DBYTES];
+    __shared__ pix_par sPar[2][kPB];
+    __shared__ int64_t sItem;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -96,7 +117,7 @@ __global__ __launch_bounds__(256, 1) void k_mfma_split16(rs_launch Lc)
 
     bool first_item = true;
     for (;;) {
-        const int64_t item = rs_next_item(Lc, &sm.item, first_item);
+        const int64_t item = rs_next_item(Lc, &sItem, first_item);
         first_item = false;
         if (item < 0) break;
         const int jidx = rs_find_job<RS_BY_ITEM>(Lc, item);
@@ -111,68 +132,114 @@ __global__ __launch_bounds__(256, 1) void k_mfma_split16(rs_launch Lc)
         const int k1 = min(J.seg_end, nsteps);
         if (k0 >= k1) continue;                      // chunk finished in an earlier segment
         const bool seg_first = k0 == 0, seg_last = k1 == nsteps;
+        const bool full_tile = n0 + TN <= J.Ns && l0 + TL <= J.L;
         const int m = it.c / J.N, r = it.c % J.N;
         const double *tx = J.ant + 3 * m;
         const double *rx = J.ant + 3 * (J.M + r);
         const int sh = J.scale[it.s];
         const float a_scale = ldexpf(1.0f, sh);
 
+        // ---- pixel parameter blocks (256 pixels), raw data prefetched one
+        // block ahead so that the global-memory latency stays hidden --------
+        float rxp = 0.f, ryp = 0.f, rzp = 0.f, rap = 0.f, rvp = 0.f;
+        auto fetch_block = [&](int blk) {
+            const int64_t p = pb + (int64_t)blk * kPB + tid;
+            if (tid < kPB && blk < nblocks && p < pe) {
+                rxp = J.x[p];
+                ryp = J.y[p];
+                rzp = J.z[p];
+                rap = J.amp[p];
+                rvp = J.vr[p];
+            } else {
+                rxp = ryp = rzp = rap = rvp = 0.f;
+            }
+        };
         auto load_block = [&](int blk) {
-            const int buf = blk & 1;
-            for (int i = tid; i < kPB; i += 256) {
-                const int64_t p = pb + (int64_t)blk * kPB + i;
+            if (tid < kPB) {
+                const int64_t p = pb + (int64_t)blk * kPB + tid;
                 pix_par q;
                 if (p < pe) {
-                    rs_pixel_args a = rs_pixel(J, tx, rx, p);
-                    q.psi_f = a.psi_f;
-                    q.b = a.b;
-                    q.beta = a.beta;
-                    q.a = a.a * a_scale;
+                    const double R = 0.5 * (rs_distance(rxp, ryp, rzp, tx) + rs_distance(rxp, ryp, rzp, rx));
+                    q.psi_f = rs_frac(R * J.Kc);
+                    q.b = R * J.Kb;
+                    q.beta = (double)rvp * J.Kd;
+                    q.a = rap * a_scale;
                 } else {
                     q.psi_f = 0.0;
                     q.b = 0.0;
                     q.beta = 0.0;
                     q.a = 0.f;
                 }
-                const float fe = frac32(q.b * 32.0), fs = frac32(q.beta * 16.0);
+                const float fe = frac32(q.b * 32.0), fs = frac32(q.beta * (double)LQ);
                 q.e32x = __builtin_amdgcn_cosf(fe);
                 q.e32y = __builtin_amdgcn_sinf(fe);
-                q.s16x = __builtin_amdgcn_cosf(fs);
-                q.s16y = __builtin_amdgcn_sinf(fs);
+                q.srx = __builtin_amdgcn_cosf(fs);
+                q.sry = __builtin_amdgcn_sinf(fs);
                 q.pad_ = 0.f;
-                sm.par[buf][i] = q;
+                sPar[blk & 1][tid] = q;
             }
+            fetch_block(blk + 1);
         };
 
         const double nrow0 = (double)(n0 + wave * WN + li);
+        // D thread mapping: pixel q = lane % 16; block group lq such that the
+        // four lq of one wave are 4 columns apart (80-byte columns: their
+        // 16-dword write runs then fall into disjoint LDS banks)
+        const int q = lane & 15;
+        const int lq = (lane >> 4) * 4 + (wave & 3) + 16 * (wave >> 2);
 
-        // D phasors of step st -> LDS buffer st & 1.  Thread: pixel q, blocks
-        // l = l0 + (tid >> 4) + 16 k; D = u - j w with u + j w = a exp(j2pi beta l).
-        auto gen_d = [&](int st) {
-            const int buf = (st / kSPB) & 1;
-            const int q = tid & 15;
-            const pix_par &pp = sm.par[buf][(st % kSPB) * kKP + q];
-            const int lq = tid >> 4;
-            const float f = frac32(pp.beta * (double)(l0 + lq));
+        // D phasors of step st -> LDS buffer dbuf, all at once (prologue).
+        // Thread: pixel q, blocks l = l0 + lq + LQ k; D = u - j w with
+        // u + j w = a exp(j2pi beta l); real column (u, w), imaginary (-w, u).
+        auto d_column = [](int k) { return ((LQ * k) >> 5) * 64 + ((LQ * k) & 31); };
+        auto gen_d = [&](int st, auto dbuf) {
+            const pix_par &pp = sPar[(st / kSPB) & 1][(st % kSPB) * kKP + q];
+            const float f = frac32(pp.beta * (double)(l0 + lq));  // binary64 reduction
             float u = pp.a * __builtin_amdgcn_cosf(f);
             float w = pp.a * __builtin_amdgcn_sinf(f);
-            const float cx = pp.s16x, cy = pp.s16y;
-            char *dh = sm.d[st & 1][0];
-            char *dl = sm.d[st & 1][1];
+            char (&db)[2][DBYTES] = decltype(dbuf)::value ? sD1 : sD0;
+            char *dh = db[0] + lq * kCS + q * 4;
+            char *dl = db[1] + lq * kCS + q * 4;
 #pragma unroll
             for (int k = 0; k < DPT; ++k) {
-                const int ll = lq + 16 * k;
-                const _Float16 uh = (_Float16)u, wh = (_Float16)w;
-                const _Float16 ul = (_Float16)(u - (float)uh), wl = (_Float16)(w - (float)wh);
-                const int colre = (ll >> 5) * 64 + (ll & 31);
-                const int colim = colre + 32;
-                *reinterpret_cast<unsigned *>(dh + colre * kCS + q * 4) = pack2(uh, wh);
-                *reinterpret_cast<unsigned *>(dh + colim * kCS + q * 4) = pack2(-wh, uh);
-                *reinterpret_cast<unsigned *>(dl + colre * kCS + q * 4) = pack2(ul, wl);
-                *reinterpret_cast<unsigned *>(dl + colim * kCS + q * 4) = pack2(-wl, ul);
-                const float un = u * cx - w * cy;
-                w = u * cy + w * cx;
+                const half2v hre = hi2(u, w), him = hi2(-w, u);
+                const half2v lre = lo2(u, w, hre), lim = lo2(-w, u, him);
+                const int cre = d_column(k) * kCS, cim = cre + 32 * kCS;
+                *reinterpret_cast<unsigned *>(dh + cre) = bits(hre);
+                *reinterpret_cast<unsigned *>(dh + cim) = bits(him);
+                *reinterpret_cast<unsigned *>(dl + cre) = bits(lre);
+                *reinterpret_cast<unsigned *>(dl + cim) = bits(lim);
+                const float un = __builtin_fmaf(u, pp.srx, -(w * pp.sry));
+                w = __builtin_fmaf(u, pp.sry, w * pp.srx);
                 u = un;
+            }
+        };
+
+        // One F pixel (matrix step ft, pixel j of the lane's group of four)
+        // of step st for every row block of this lane -> hi and lo operands.
+        struct fops {
+            half8 h[2][RB], l[2][RB];
+        };
+        auto gen_f_pixel = [&](int st, int ft, int j, fops &fo) {
+            const pix_par &pf = sPar[(st / kSPB) & 1][(st % kSPB) * kKP + 8 * ft + 4 * g + j];
+            const float f = frac32(__builtin_fma(pf.b, nrow0, pf.psi_f));
+            float cv = __builtin_amdgcn_cosf(f);
+            float sv = __builtin_amdgcn_sinf(f);
+            const float ex = pf.e32x, ey = pf.e32y;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const half2v h = hi2(cv, sv);
+                u32x4 vh = __builtin_bit_cast(u32x4, fo.h[ft][rb]);
+                u32x4 vl = __builtin_bit_cast(u32x4, fo.l[ft][rb]);
+                vh[j] = bits(h);
+                vl[j] = bits(lo2(cv, sv, h));
+                fo.h[ft][rb] = __builtin_bit_cast(half8, vh);
+                fo.l[ft][rb] = __builtin_bit_cast(half8, vl);
+                if (rb + 1 < RB) {
+                    const float cn = __builtin_fmaf(cv, ex, -(sv * ey));
+                    sv = __builtin_fmaf(cv, ey, sv * ex);
+                    cv = cn;
+                }
             }
         };
 
@@ -189,14 +256,16 @@ __global__ __launch_bounds__(256, 1) void k_mfma_split16(rs_launch Lc)
                     for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.f;
         } else {
             // resume: raw accumulators parked by the previous segment
+            int rli = li, rg = g;
+            asm volatile("" : "+v"(rli), "+v"(rg));
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int k = 0; k < CB / 2; ++k) {
-                    const int l = l0 + 32 * k + li;
+                    const int l = l0 + 32 * k + rli;
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
-                        const int n = n0 + wave * WN + rb * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
+                        const int n = n0 + wave * WN + rb * 32 + 8 * (e >> 2) + 4 * rg + (e & 3);
                         float2 v = make_float2(0.f, 0.f);
                         if (n < J.Ns && l < J.L) v = part[(int64_t)l * J.Ns + n];
                         acc[rb][2 * k][e] = v.x;
@@ -205,88 +274,157 @@ __global__ __launch_bounds__(256, 1) void k_mfma_split16(rs_launch Lc)
                 }
         }
 
-        // F phasors of step st, matrix step t only (see gen_f).
-        auto gen_f_t = [&](int st, int t, half8 (&fh)[RB], half8 (&fl)[RB]) {
-            const int buf = (st / kSPB) & 1;
-            const int base = (st % kSPB) * kKP + 8 * t + 4 * g;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const pix_par &pp = sm.par[buf][base + j];
-                const float f = frac32(pp.psi_f + rs_frac(pp.b * nrow0));
-                float cv = __builtin_amdgcn_cosf(f);
-                float sv = __builtin_amdgcn_sinf(f);
-                const float ex = pp.e32x, ey = pp.e32y;
+        // One step, written as an explicit software pipeline: 2 CB groups,
+        // each with the B operands of one column block (loaded one group
+        // ahead), its RB x 3 matrix products, and one slice of the next
+        // step's phasor work (a D element into the other LDS buffer, or an F
+        // pixel into the other register set).  A scheduling fence after
+        // every group keeps the slices spread over the matrix instructions.
+        // What is evaluated after the last step is never used.
+        constexpr int NG = 2 * CB;                  // groups per step
+        constexpr int FG = NG - DPT;                // groups evaluating F
+        constexpr int FPG = (8 + FG - 1) / FG;      // F pixels per such group
+        auto step = [&](int st, auto cur, auto nxt, const fops &fc, fops &fn) {
+            if ((st % kSPB) == 0 && st / kSPB + 1 < nblocks) load_block(st / kSPB + 1);
+            const int s1 = st + 1;
+            const pix_par &pd = sPar[(s1 / kSPB) & 1][(s1 % kSPB) * kKP + q];
+            const float fd = frac32(pd.beta * (double)(l0 + lq));
+            float u = pd.a * __builtin_amdgcn_cosf(fd);
+            float w = pd.a * __builtin_amdgcn_sinf(fd);
+            const float cx = pd.srx, cy = pd.sry;
+            char (&dbn)[2][DBYTES] = decltype(nxt)::value ? sD1 : sD0;
+            char *dwh = dbn[0] + lq * kCS + q * 4;
+            char *dwl = dbn[1] + lq * kCS + q * 4;
+            // lane offset through an empty asm statement: the per-block
+            // constants then fold into the LDS instructions' offset fields
+            int lo = li * kCS + 16 * g;
+            asm volatile("" : "+v"(lo));
+            const char (&dbc)[2][DBYTES] = decltype(cur)::value ? sD1 : sD0;
+            const char *drh = dbc[0] + lo;
+            const char *drl = dbc[1] + lo;
+            auto boff = [](int gi) { return (gi % CB) * 32 * kCS + 32 * (gi / CB); };
+            half8 nbh = *reinterpret_cast<const half8 *>(drh + boff(0));
+            half8 nbl = *reinterpret_cast<const half8 *>(drl + boff(0));
+            // The work of one group gi: B operands (prefetched one group
+            // ahead) and the RB x 3 matrix products, and separately the
+            // phasor slice gi of the next step.
+            auto mfma_group = [&](int gi) {
+                const int t = gi / CB, cb = gi % CB;
+                const half8 bh = nbh, bl = nbl;
+                if (gi + 1 < NG) {
+                    nbh = *reinterpret_cast<const half8 *>(drh + boff(gi + 1));
+                    nbl = *reinterpret_cast<const half8 *>(drl + boff(gi + 1));
+                }
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
-                    const _Float16 ch = (_Float16)cv, shh = (_Float16)sv;
-                    fh[rb][2 * j] = ch;
-                    fh[rb][2 * j + 1] = shh;
-                    fl[rb][2 * j] = (_Float16)(cv - (float)ch);
-                    fl[rb][2 * j + 1] = (_Float16)(sv - (float)shh);
-                    if (rb + 1 < RB) {
-                        const float cn = cv * ex - sv * ey;
-                        sv = cv * ey + sv * ex;
-                        cv = cn;
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], bh, acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], bl, acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.l[t][rb], bh, acc[rb][cb], 0, 0, 0);
+                }
+            };
+            auto valu_slice = [&](int gi) {
+                if (gi < DPT) {
+                    const half2v hre = hi2(u, w), him = hi2(-w, u);
+                    const half2v lre = lo2(u, w, hre), lim = lo2(-w, u, him);
+                    const int cre = d_column(gi) * kCS, cim = cre + 32 * kCS;
+                    *reinterpret_cast<unsigned *>(dwh + cre) = bits(hre);
+                    *reinterpret_cast<unsigned *>(dwh + cim) = bits(him);
+                    *reinterpret_cast<unsigned *>(dwl + cre) = bits(lre);
+                    *reinterpret_cast<unsigned *>(dwl + cim) = bits(lim);
+                    const float un = __builtin_fmaf(u, cx, -(w * cy));
+                    w = __builtin_fmaf(u, cy, w * cx);
+                    u = un;
+                } else {
+#pragma unroll
+                    for (int k8 = 0; k8 < FPG; ++k8) {
+                        const int fp = (gi - DPT) * FPG + k8;  // F pixel 0..7 of step s1
+                        if (fp < 8) gen_f_pixel(s1, fp >> 2, fp & 3, fn);
                     }
                 }
-            }
-        };
-
-        auto mfma_t = [&](int st, int t, const half8 (&fh)[RB], const half8 (&fl)[RB]) {
-            const char *dh = sm.d[st & 1][0];
-            const char *dl = sm.d[st & 1][1];
+            };
+            if (NW == 8 && PHASE && wave >= 4) {
+                // second wave of each SIMD: phasor work first, then the
+                // matrix work, so that it complements the first wave
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const int off = (cb * 32 + li) * kCS + 32 * t + 16 * g;
-                const half8 bh = *reinterpret_cast<const half8 *>(dh + off);
-                const half8 bl = *reinterpret_cast<const half8 *>(dl + off);
+                for (int gi = 0; gi < NG; ++gi) {
+                    valu_slice(gi);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[rb], bh, acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[rb], bl, acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[rb], bh, acc[rb][cb], 0, 0, 0);
+                for (int gi = 0; gi < NG; ++gi) {
+                    mfma_group(gi);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else if (NW == 8 && PHASE) {
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi) {
+                    mfma_group(gi);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi) {
+                    valu_slice(gi);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+#pragma unroll
+                for (int gi = 0; gi < NG; ++gi) {
+                    mfma_group(gi);
+                    valu_slice(gi);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
+            __syncthreads();
         };
 
-        // Operands of matrix step t: f0 (t = 0) and f1 (t = 1).  Each step
-        // issues the matrix work of st while the next step's D (other LDS
-        // buffer) and F (each half as soon as its registers are consumed)
-        // are evaluated.  What is evaluated after the last step is unused.
-        half8 f0h[RB], f0l[RB], f1h[RB], f1l[RB];
+        fops fa, fb;
         __syncthreads();  // previous item's readers of the LDS buffers are done
+        fetch_block(k0 / kSPB);
         load_block(k0 / kSPB);
         __syncthreads();
-        gen_d(k0);
-        gen_f_t(k0, 0, f0h, f0l);
-        gen_f_t(k0, 1, f1h, f1l);
+        gen_d(k0, buf0_t{});  // k0 is even: buffer 0
+#pragma unroll
+        for (int fp = 0; fp < 8; ++fp) gen_f_pixel(k0, fp >> 2, fp & 3, fa);
         __syncthreads();
-        for (int st = k0; st < k1; ++st) {
-            if ((st % kSPB) == 0 && st / kSPB + 1 < nblocks) load_block(st / kSPB + 1);
-            gen_d(st + 1);
-            mfma_t(st, 0, f0h, f0l);
-            gen_f_t(st + 1, 0, f0h, f0l);
-            mfma_t(st, 1, f1h, f1l);
-            gen_f_t(st + 1, 1, f1h, f1l);
-            __syncthreads();
+        for (int st = k0; st < k1; st += 2) {
+            step(st, buf0_t{}, buf1_t{}, fa, fb);
+            if (st + 1 >= k1) break;
+            step(st + 1, buf1_t{}, buf0_t{}, fb, fa);
         }
 
         // ---- park or write the partial tile ---------------------------------
+        // Lane coordinates pass through an empty asm statement so that the
+        // store addresses are computed here, not hoisted above the step loop.
+        int wli = li, wg = g;
+        asm volatile("" : "+v"(wli), "+v"(wg));
+        auto wn_of = [&](int rb, int e) { return n0 + wave * WN + rb * 32 + 8 * (e >> 2) + 4 * wg + (e & 3); };
         const float osc = seg_last ? ldexpf(1.0f, -sh) : 1.0f;
+        if (full_tile) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int k = 0; k < CB / 2; ++k) {
-                const int l = l0 + 32 * k + li;
-                if (l >= J.L) continue;
+                for (int k = 0; k < CB / 2; ++k) {
+                    float2 *row = part + (int64_t)(l0 + 32 * k + wli) * J.Ns;
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int n = n0 + wave * WN + rb * 32 + 8 * (e >> 2) + 4 * g + (e & 3);
-                    if (n < J.Ns)
-                        part[(int64_t)l * J.Ns + n] =
-                            make_float2(acc[rb][2 * k][e] * osc, acc[rb][2 * k + 1][e] * osc);
+                    for (int e = 0; e < 16; ++e)
+                        row[wn_of(rb, e)] = make_float2(acc[rb][2 * k][e] * osc, acc[rb][2 * k + 1][e] * osc);
                 }
-            }
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int k = 0; k < CB / 2; ++k) {
+                    const int l = l0 + 32 * k + wli;
+                    if (l >= J.L) continue;
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int n = wn_of(rb, e);
+                        if (n < J.Ns)
+                            part[(int64_t)l * J.Ns + n] =
+                                make_float2(acc[rb][2 * k][e] * osc, acc[rb][2 * k + 1][e] * osc);
+                    }
+                }
+        }
     }
 }
 
@@ -316,29 +454,47 @@ __global__ __launch_bounds__(256) void k_chunk_scale(rs_launch Lc)
     }
 }
 
-template <int WN, int TL>
+// Phase-shifted waves (RS_MFMA_PHASE=0 disables, for tuning).
+bool phase_enabled()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("RS_MFMA_PHASE");
+        return !(v && v[0] == '0');
+    }();
+    return on;
+}
+
+template <int WN, int TL, int NW>
 void launch_one(const rs_launch &L, int grid, hipStream_t st)
 {
-    const size_t smem = sizeof(mfma_smem<WN, TL>);
-    static std::once_flag once;
-    std::call_once(once, [smem] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mfma_split16<WN, TL>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    });
-    hipLaunchKernelGGL((k_mfma_split16<WN, TL>), dim3(grid), dim3(256), smem, st, L);
+    if (NW == 8 && phase_enabled())
+        hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, true>), dim3(grid), dim3(64 * NW), 0, st, L);
+    else
+        hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, false>), dim3(grid), dim3(64 * NW), 0, st, L);
 }
 
 }  // namespace
 
-void rs_launch_mfma(const rs_launch &L, int wn, int tl, int grid, hipStream_t st)
+// Tile shapes built into the library: rows per wave x columns x waves.
+bool rs_mfma_shape_supported(int wn, int tl, int nw)
 {
-    if (tl == 64) {
-        if (wn == 32) launch_one<32, 64>(L, grid, st);
-        else if (wn == 64) launch_one<64, 64>(L, grid, st);
-        else launch_one<128, 64>(L, grid, st);
+    return (tl == 128 && ((wn == 64 && nw == 4) || (wn == 32 && (nw == 4 || nw == 8)))) ||
+           (tl == 64 && ((wn == 32 && (nw == 4 || nw == 8)) || (wn == 64 && (nw == 4 || nw == 8)) ||
+                         (wn == 128 && nw == 4)));
+}
+
+void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, int grid, hipStream_t st)
+{
+    if (tl == 128) {
+        if (wn == 64) launch_one<64, 128, 4>(L, grid, st);
+        else if (nw == 8) launch_one<32, 128, 8>(L, grid, st);
+        else launch_one<32, 128, 4>(L, grid, st);
     } else {
-        if (wn == 32) launch_one<32, 128>(L, grid, st);
-        else launch_one<64, 128>(L, grid, st);
+        if (wn == 32 && nw == 8) launch_one<32, 64, 8>(L, grid, st);
+        else if (wn == 32) launch_one<32, 64, 4>(L, grid, st);
+        else if (wn == 64 && nw == 8) launch_one<64, 64, 8>(L, grid, st);
+        else if (wn == 64) launch_one<64, 64, 4>(L, grid, st);
+        else launch_one<128, 64, 4>(L, grid, st);
     }
 }
 

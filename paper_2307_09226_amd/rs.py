@@ -14,7 +14,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "librs.so")
+# RS_LIBRARY selects another build of the library (e.g. an instrumented one)
+LIB_PATH = os.environ.get("RS_LIBRARY") or os.path.join(_PKG, "librs.so")
 
 RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_UNSUPPORTED, RS_E_BUSY, RS_E_NOT_FOUND = range(7)
 RS_FORM_FP64_DIRECT, RS_FORM_MFMA_SPLIT16 = 0, 1
