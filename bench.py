@@ -33,6 +33,32 @@ PEAK_FP64 = 78.6e12    # fp64 vector flop/s, MI355X
 FLOP_MFMA = 24         # 3 split products x complex MAC (4 real MACs) x 2
 FLOP_PLAIN = 8         # one binary64 complex MAC
 
+# HBM bytes per launch of k_mfma_split16 on the headline frame: rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters
+# read for a 1 GiB device copy (fetch x 2.0, write x 1.0).  They hold only for
+# the kernel sources they were taken on; any change to those sources turns
+# the figure into null until the counters are taken again.
+TRAFFIC_SOURCES = ("rs_mfma.hip", "rs_device.h", "rs_internal.h")
+TRAFFIC = {"sources_sha256": "54b48807efa4aa6218420d03794e3a580b4378d10fc28e8b0022906123bfc91a",
+           "fetch_bytes": 10.80e6, "write_bytes": 67.10e6}
+
+
+# Offered load of the serving leg, frozen so that latencies stay comparable
+# between runs: 0.6 x the capacity measured with the whole 48-request pool
+# queued at once (4.44e13 terms/s) / the pool's mean request (1.94e11 terms).
+SERVING_RATE = 137.5
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2307_09226_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -41,10 +67,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline single-frame measurement")
-    ap.add_argument("--serving-requests", type=int, default=400)
-    ap.add_argument("--serving-rate", type=float, default=0.0,
-                    help="requests/s; 0 = 0.6 x the measured capacity")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
+                    help="requests/s; 0 = 0.6 x the capacity measured in this run")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run 5 device-to-device copies of this many MiB (the "
+                         "calibration kernel for the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -121,6 +150,9 @@ def main():
               "not part of this build", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
+        return
     from paper_2307_09226_amd import rs, scenes
 
     dev = "cuda:0"
@@ -156,9 +188,11 @@ def main():
                    "plan": json.loads(plan.describe(px.P))},
         "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP16 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP16, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP16, "traffic": measured_traffic(),
                      "kernel": "k_mfma_split16", "kernel_ms": kavg,
-                     "flop_per_term": FLOP_MFMA, "terms_per_launch": terms},
+                     "flop_per_term": FLOP_MFMA, "terms_per_launch": terms,
+                     "traffic_unit": "HBM bytes per launch",
+                     "algorithmic_bytes": 20 * px.P + 8 * radar.C * radar.L * radar.Ns},
     }
     torch.cuda.synchronize()
     out["parity"] = parity_sampled(radar, px, cube.cpu().numpy())
@@ -219,9 +253,24 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def copy_probe(mib):
+    """A plain copy of known size: reads and writes mib MiB once per launch."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "launches": 5}), flush=True)
+
+
 def serving(rs, scenes, dev, args):
     """Poisson arrivals of mixed cube requests at a fixed rate; latency is
-    completion minus submission per request."""
+    completion minus submission per request.  Capacity (terms/s with every
+    pool request queued at once, measured twice; the first pass is the
+    warm-up) is reported beside the offered load."""
     import torch
     pool_n = 48
     pool = scenes.serving_requests(pool_n)
@@ -233,49 +282,56 @@ def serving(rs, scenes, dev, args):
             plans[key] = rs.rs_cube_plan(q.radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64,
                                          max_pixels=262144)
         items.append((plans[key], rs.DevicePixels.from_host(q.pixels, dev), q.terms))
+    mean_terms = float(np.mean([t for _, _, t in items]))
     max_slots = 16
     sess = rs.Session(hbm_budget=16 << 30, max_slots=max_slots, queue_cap=100000)
-    # cubes are reused round-robin; each request writes its own buffer
+    # one output buffer per pool entry; a request writes its entry's buffer
     bufs = [rs.new_cube(p, dev) for p, _, _ in items]
     torch.cuda.synchronize()
 
-    def run(n, rate, seed):
-        arr = scenes.poisson_arrivals(n, rate, seed=seed) if rate > 0 else np.zeros(n)
-        order = np.random.default_rng(seed).integers(0, len(items), n)
+    def run(order, arrivals):
         tickets = []
         terms = 0.0
         t0 = time.perf_counter()
-        for i in range(n):
-            while time.perf_counter() - t0 < arr[i]:
+        for i, k in enumerate(order):
+            while time.perf_counter() - t0 < arrivals[i]:
                 time.sleep(0.0002)
-            p, d, tm = items[order[i]]
-            tickets.append(sess.submit(p, d, bufs[order[i]]))
+            p, d, tm = items[k]
+            tickets.append(sess.submit(p, d, bufs[k]))
             terms += tm
         sess.drain()
         wall = time.perf_counter() - t0
-        lat = []
-        for t in tickets:
+        lat, big = [], []
+        for t, k in zip(tickets, order):
             st, (ts, ta, td) = sess.poll(t)
             assert st == rs.RS_REQ_DONE, st
             lat.append((td - ts) * 1e-6)
         return wall, terms, lat
 
-    # capacity: everything submitted at once
-    warm_n = 64
-    wall, terms, _ = run(warm_n, 0.0, 1)
-    cap_rps = warm_n / wall
-    rate = args.serving_rate if args.serving_rate > 0 else 0.6 * cap_rps
+    # capacity: every pool request queued at once (twice; the second is timed)
+    allk = np.arange(len(items))
+    run(allk, np.zeros(len(items)))
+    wall, terms, _ = run(allk, np.zeros(len(items)))
+    cap_terms = terms / wall
+    rate = args.serving_rate if args.serving_rate > 0 else 0.6 * cap_terms / mean_terms
     n = args.serving_requests
-    wall, terms, lat = run(n, rate, 7)
+    order = np.random.default_rng(7).integers(0, len(items), n)
+    arrivals = scenes.poisson_arrivals(n, rate, seed=7)
+    wall, terms, lat = run(order, arrivals)
     st = sess.stats()
     sess.close()
     for p in plans.values():
         p.close()
+    lat = np.asarray(lat)
+    sizes = np.array([items[k][2] for k in order])
+    small = sizes <= np.median(sizes)
     return {"workload": "Poisson arrivals of mixed requests (1x4, 3x4, 12x16 arrays; Ns 128/256/512; "
-                        "L 64/128/256; 4k-262k pixels), pool of 48 seeded requests",
-            "capacity_req_per_s": cap_rps, "rate_req_per_s": rate, "requests": n,
+                        "L 64/128/256; 4k-262k pixels), drawn from a pool of 48 seeded requests",
+            "pool_mean_terms": mean_terms, "capacity_terms_per_s": cap_terms,
+            "rate_req_per_s": rate, "offered_terms_per_s": rate * mean_terms, "requests": n,
             "throughput_req_per_s": n / wall, "terms_per_s": terms / wall,
             "latency_p50_ms": pct(lat, 50), "latency_p99_ms": pct(lat, 99),
+            "latency_p50_ms_small_half": pct(lat[small], 50), "latency_p99_ms_small_half": pct(lat[small], 99),
             "launches": int(st["launches"]), "footprint_peak_bytes": int(st["footprint_peak"]),
             "max_slots": max_slots}
 
