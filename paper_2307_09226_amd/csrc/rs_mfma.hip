@@ -68,7 +68,8 @@ struct __align__(16) pix_par {
     float pad_;
 };
 
-__device__ __forceinline__ float frac32(double v) { return (float)rs_frac(v); }
+// frac in binary64 (v_fract_f64: v - floor(v), held below 1), then binary32
+__device__ __forceinline__ float frac32(double v) { return (float)__builtin_amdgcn_fract(v); }
 
 // hi = rne16(x) for a pair, packed in one register (v_cvt_pk_f16_f32)
 __device__ __forceinline__ half2v hi2(float x, float y) { return half2v{(_Float16)x, (_Float16)y}; }
@@ -87,6 +88,22 @@ __device__ __forceinline__ half2v lo2(float x, float y, half2v h)
 }
 
 __device__ __forceinline__ unsigned bits(half2v v) { return __builtin_bit_cast(unsigned, v); }
+
+// Pins a binary32 value: the empty asm statement hides how it was produced,
+// so the compiler cannot fuse a later fp16 conversion with the multiply-add
+// that produced it (that would round the exact result once, to fp16).  Every
+// code path then yields the same bits for the same phasor, which keeps a
+// cube independent of how its steps were split over launches.
+__device__ __forceinline__ void pin(float &u, float &w) { asm("" : "+v"(u), "+v"(w)); }
+
+// (u + j w) * (rx + j ry) in binary32
+__device__ __forceinline__ void rot(float &u, float &w, float rx, float ry)
+{
+    float un = __builtin_fmaf(u, rx, -(w * ry));
+    w = __builtin_fmaf(u, ry, w * rx);
+    u = un;
+    pin(u, w);
+}
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef std::integral_constant<int, 0> buf0_t;
@@ -197,6 +214,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             const float f = frac32(pp.beta * (double)(l0 + lq));  // binary64 reduction
             float u = pp.a * __builtin_amdgcn_cosf(f);
             float w = pp.a * __builtin_amdgcn_sinf(f);
+            pin(u, w);
             char (&db)[2][DBYTES] = decltype(dbuf)::value ? sD1 : sD0;
             char *dh = db[0] + lq * kCS + q * 4;
             char *dl = db[1] + lq * kCS + q * 4;
@@ -209,9 +227,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 *reinterpret_cast<unsigned *>(dh + cim) = bits(him);
                 *reinterpret_cast<unsigned *>(dl + cre) = bits(lre);
                 *reinterpret_cast<unsigned *>(dl + cim) = bits(lim);
-                const float un = __builtin_fmaf(u, pp.srx, -(w * pp.sry));
-                w = __builtin_fmaf(u, pp.sry, w * pp.srx);
-                u = un;
+                rot(u, w, pp.srx, pp.sry);
             }
         };
 
@@ -235,11 +251,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 vl[j] = bits(lo2(cv, sv, h));
                 fo.h[ft][rb] = __builtin_bit_cast(half8, vh);
                 fo.l[ft][rb] = __builtin_bit_cast(half8, vl);
-                if (rb + 1 < RB) {
-                    const float cn = __builtin_fmaf(cv, ex, -(sv * ey));
-                    sv = __builtin_fmaf(cv, ey, sv * ex);
-                    cv = cn;
-                }
+                if (rb + 1 < RB) rot(cv, sv, ex, ey);
             }
         };
 
@@ -274,23 +286,35 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 }
         }
 
-        // One step, written as an explicit software pipeline: 2 CB groups,
-        // each with the B operands of one column block (loaded one group
-        // ahead), its RB x 3 matrix products, and one slice of the next
-        // step's phasor work (a D element into the other LDS buffer, or an F
-        // pixel into the other register set).  A scheduling fence after
-        // every group keeps the slices spread over the matrix instructions.
+        // One step, written as an explicit software pipeline.  Matrix part:
+        // NG = 2 CB groups, each the RB x 3 products of one column block and
+        // one 16-deep matrix step, with its B operands (hi, lo) loaded kBD
+        // groups ahead into a ring of registers; a scheduling fence after
+        // every group keeps the loads where they are.  Vector part: NG
+        // slices, the D phasors of the next step (into the other LDS buffer)
+        // and the F pixels of step fstep (into fn).
+        //   Phase-shifted waves (NW = 8): the two waves of a SIMD run the two
+        // parts in opposite order, so one issues matrix instructions while
+        // the other evaluates phasors.  The first wave evaluates F of the
+        // next step after its products, the second F of the current step
+        // before them; either way the F registers are dead when they are
+        // rewritten, so one set suffices.
+        //   Otherwise the vector slices are interleaved with the groups and F
+        // is double-buffered.
         // What is evaluated after the last step is never used.
         constexpr int NG = 2 * CB;                  // groups per step
-        constexpr int FG = NG - DPT;                // groups evaluating F
-        constexpr int FPG = (8 + FG - 1) / FG;      // F pixels per such group
-        auto step = [&](int st, auto cur, auto nxt, const fops &fc, fops &fn) {
+        constexpr int FG = NG - DPT;                // slices evaluating F
+        constexpr int FPG = (8 + FG - 1) / FG;      // F pixels per such slice
+        constexpr bool kShift = NW == 8 && PHASE;
+        constexpr int kBD = kShift ? 2 : 1;         // B prefetch distance in groups
+        auto step = [&](int st, auto cur, auto nxt, const fops &fc, fops &fn, int fstep) {
             if ((st % kSPB) == 0 && st / kSPB + 1 < nblocks) load_block(st / kSPB + 1);
             const int s1 = st + 1;
             const pix_par &pd = sPar[(s1 / kSPB) & 1][(s1 % kSPB) * kKP + q];
             const float fd = frac32(pd.beta * (double)(l0 + lq));
             float u = pd.a * __builtin_amdgcn_cosf(fd);
             float w = pd.a * __builtin_amdgcn_sinf(fd);
+            pin(u, w);
             const float cx = pd.srx, cy = pd.sry;
             char (&dbn)[2][DBYTES] = decltype(nxt)::value ? sD1 : sD0;
             char *dwh = dbn[0] + lq * kCS + q * 4;
@@ -303,24 +327,25 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             const char *drh = dbc[0] + lo;
             const char *drl = dbc[1] + lo;
             auto boff = [](int gi) { return (gi % CB) * 32 * kCS + 32 * (gi / CB); };
-            half8 nbh = *reinterpret_cast<const half8 *>(drh + boff(0));
-            half8 nbl = *reinterpret_cast<const half8 *>(drl + boff(0));
-            // The work of one group gi: B operands (prefetched one group
-            // ahead) and the RB x 3 matrix products, and separately the
-            // phasor slice gi of the next step.
+            half8 bh[kBD + 1], bl[kBD + 1];
+            auto load_b = [&](int gi) {
+                bh[gi % (kBD + 1)] = *reinterpret_cast<const half8 *>(drh + boff(gi));
+                bl[gi % (kBD + 1)] = *reinterpret_cast<const half8 *>(drl + boff(gi));
+            };
             auto mfma_group = [&](int gi) {
+                if (gi + kBD < NG) load_b(gi + kBD);
                 const int t = gi / CB, cb = gi % CB;
-                const half8 bh = nbh, bl = nbl;
-                if (gi + 1 < NG) {
-                    nbh = *reinterpret_cast<const half8 *>(drh + boff(gi + 1));
-                    nbl = *reinterpret_cast<const half8 *>(drl + boff(gi + 1));
-                }
+                const half8 h = bh[gi % (kBD + 1)], l = bl[gi % (kBD + 1)];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], bh, acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], bl, acc[rb][cb], 0, 0, 0);
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.l[t][rb], bh, acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], h, acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], l, acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.l[t][rb], h, acc[rb][cb], 0, 0, 0);
                 }
+            };
+            auto mfma_prologue = [&] {
+#pragma unroll
+                for (int gi = 0; gi < kBD && gi < NG; ++gi) load_b(gi);
             };
             auto valu_slice = [&](int gi) {
                 if (gi < DPT) {
@@ -331,42 +356,38 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                     *reinterpret_cast<unsigned *>(dwh + cim) = bits(him);
                     *reinterpret_cast<unsigned *>(dwl + cre) = bits(lre);
                     *reinterpret_cast<unsigned *>(dwl + cim) = bits(lim);
-                    const float un = __builtin_fmaf(u, cx, -(w * cy));
-                    w = __builtin_fmaf(u, cy, w * cx);
-                    u = un;
+                    rot(u, w, cx, cy);
                 } else {
 #pragma unroll
                     for (int k8 = 0; k8 < FPG; ++k8) {
-                        const int fp = (gi - DPT) * FPG + k8;  // F pixel 0..7 of step s1
-                        if (fp < 8) gen_f_pixel(s1, fp >> 2, fp & 3, fn);
+                        const int fp = (gi - DPT) * FPG + k8;  // F pixel 0..7 of step fstep
+                        if (fp < 8) gen_f_pixel(fstep, fp >> 2, fp & 3, fn);
                     }
                 }
             };
-            if (NW == 8 && PHASE && wave >= 4) {
+            if (kShift && wave >= 4) {
                 // second wave of each SIMD: phasor work first, then the
                 // matrix work, so that it complements the first wave
 #pragma unroll
-                for (int gi = 0; gi < NG; ++gi) {
-                    valu_slice(gi);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                for (int gi = 0; gi < NG; ++gi) valu_slice(gi);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_prologue();
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     mfma_group(gi);
                     __builtin_amdgcn_sched_barrier(0);
                 }
-            } else if (NW == 8 && PHASE) {
+            } else if (kShift) {
+                mfma_prologue();
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     mfma_group(gi);
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
-                for (int gi = 0; gi < NG; ++gi) {
-                    valu_slice(gi);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                for (int gi = 0; gi < NG; ++gi) valu_slice(gi);
             } else {
+                mfma_prologue();
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     mfma_group(gi);
@@ -383,13 +404,24 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         load_block(k0 / kSPB);
         __syncthreads();
         gen_d(k0, buf0_t{});  // k0 is even: buffer 0
+        if (!kShift || wave < 4) {
 #pragma unroll
-        for (int fp = 0; fp < 8; ++fp) gen_f_pixel(k0, fp >> 2, fp & 3, fa);
+            for (int fp = 0; fp < 8; ++fp) gen_f_pixel(k0, fp >> 2, fp & 3, fa);
+        }
         __syncthreads();
-        for (int st = k0; st < k1; st += 2) {
-            step(st, buf0_t{}, buf1_t{}, fa, fb);
-            if (st + 1 >= k1) break;
-            step(st + 1, buf1_t{}, buf0_t{}, fb, fa);
+        if constexpr (kShift) {
+            const int fofs = wave < 4 ? 1 : 0;  // F of the next step / of this step
+            for (int st = k0; st < k1; st += 2) {
+                step(st, buf0_t{}, buf1_t{}, fa, fa, st + fofs);
+                if (st + 1 >= k1) break;
+                step(st + 1, buf1_t{}, buf0_t{}, fa, fa, st + 1 + fofs);
+            }
+        } else {
+            for (int st = k0; st < k1; st += 2) {
+                step(st, buf0_t{}, buf1_t{}, fa, fb, st + 1);
+                if (st + 1 >= k1) break;
+                step(st + 1, buf1_t{}, buf0_t{}, fb, fa, st + 2);
+            }
         }
 
         // ---- park or write the partial tile ---------------------------------

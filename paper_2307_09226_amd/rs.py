@@ -102,6 +102,11 @@ def _load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"librs.so not found at {path}: build it first "
                            "(python -c 'import __graft_entry__ as g; g.build()')")
+    # PyTorch ships its own copy of the HIP runtime.  Loading it first makes
+    # librs.so bind to that same copy (its soname matches); loaded the other
+    # way round the process would hold two HIP runtimes, and whichever
+    # initialises the GPU second finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -110,3 +110,24 @@ def test_ws_variant_equals_allocating_variant():
         a = synth(radar, px, form, 0)
         b = synth(radar, px, form, 0, ws=True)
         assert np.array_equal(a, b)
+
+
+def test_library_first_then_torch_share_one_runtime():
+    """A process that loads the binding and creates a plan before touching
+    torch's GPU state must still see the device from torch (one HIP runtime
+    in the process)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2307_09226_amd import rs, scenes\n"
+            "plan = rs.rs_cube_plan(scenes.radar_small(), rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=64)\n"
+            "import torch\n"
+            "assert torch.cuda.is_available()\n"
+            "cube = rs.new_cube(plan)\n"
+            "px = rs.DevicePixels.from_host(scenes.tiny_scene(1, 64))\n"
+            "rs.rs_beat_synthesize(plan, px, cube)\n"
+            "torch.cuda.synchronize()\n"
+            "print('ok')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stderr[-2000:]
