@@ -38,7 +38,7 @@ __all__ = [
     "C0", "Radar", "Pixels", "Room", "Pedestrian", "ula_geometry", "radar_for",
     "draw_room", "draw_pedestrian", "render", "cull", "concat", "scene_small",
     "scene_frame", "animation_frames", "serving_requests", "poisson_arrivals",
-    "ServingRequest", "tiny_scene",
+    "ServingRequest", "tiny_scene", "CircleWalk", "circle_walk",
 ]
 
 
@@ -319,6 +319,49 @@ def animation_frames(seed: int = 3, nframes: int = 64, dt: float = 1.0 / 30.0,
         side = int(min(max_grid, max(1, round(math.sqrt(target)))))
         frames.append(cull(render(frng, room, ped, side, side)))
     return frames
+
+
+@dataclasses.dataclass
+class CircleWalk:
+    """Frames of the walking-circle scenario and the pedestrian's ground
+    truth per frame: centre [F][3], velocity [F][3] and the radial velocity of
+    the centre seen from the radar (positive when approaching)."""
+    frames: List[Pixels]
+    centres: np.ndarray
+    velocities: np.ndarray
+    v_radial: np.ndarray
+    speed: float
+    fps: float
+
+
+def circle_walk(seed: int = 5, nframes: int = 100, fps: float = 24.0, radius: float = 3.0,
+                centre_xy: Tuple[float, float] = (0.0, 5.5), grid: int = 256,
+                room_wd: Tuple[float, float] = (12.0, 10.0), theta0: float = 0.0,
+                frame_ids: Optional[Sequence[int]] = None) -> CircleWalk:
+    """Stand-in for the walking scenario of Sec. III: the ellipsoid pedestrian
+    walks counter-clockwise at constant speed around a circle of `radius`
+    metres centred at `centre_xy`, one full turn over `nframes` frames at
+    `fps` (2 pi 3 m / (100 / 24 s) = 4.52 m/s for the paper's numbers), in a
+    fixed room of width x depth `room_wd`.  Frame f renders the pedestrian at
+    angle theta0 + 2 pi f / nframes with strengths drawn from the generator
+    seeded by (seed, f).  frame_ids renders only those frames of the walk."""
+    room = Room(W=float(room_wd[0]), D=float(room_wd[1]))
+    semi = np.array([0.20, 0.15, 0.85])
+    zc = -room.H / 2.0 + semi[2]
+    speed = 2.0 * math.pi * radius * fps / nframes
+    frames, centres, vels, vrad = [], [], [], []
+    for f in (range(nframes) if frame_ids is None else frame_ids):
+        th = theta0 + 2.0 * math.pi * f / nframes
+        c = np.array([centre_xy[0] + radius * math.cos(th), centre_xy[1] + radius * math.sin(th), zc])
+        v = np.array([-speed * math.sin(th), speed * math.cos(th), 0.0])
+        ped = Pedestrian(centre=c, velocity=v, semi_axes=semi)
+        frng = np.random.default_rng([seed, f])
+        frames.append(cull(render(frng, room, ped, grid, grid)))
+        centres.append(c)
+        vels.append(v)
+        vrad.append(-float(v @ (c / np.linalg.norm(c))))
+    return CircleWalk(frames=frames, centres=np.array(centres), velocities=np.array(vels),
+                      v_radial=np.array(vrad), speed=speed, fps=fps)
 
 
 @dataclasses.dataclass
