@@ -205,6 +205,49 @@ void rs_session_destroy(rs_session *s);
  * affected). */
 rs_status rs_session_inject_failure(rs_session *s, int32_t count);
 
+/* -------------------------------------------------- range-Doppler maps -- */
+/* The processing the paper applies to each simulated cube (Sec. III): an FFT
+ * over each coherent processing interval (one cube) gives the range-Doppler
+ * map, and the velocity of the map's strongest cell, one per CPI, forms the
+ * Doppler-time series that is compared with the ground-truth velocity.
+ *
+ *   X_c[k][d] = sum_l sum_n Y[c][l][n] exp(-j2pi k n / Ns) exp(+j2pi d l / L)
+ *   power[k][d] = sum_c |X_c[k][d]|^2         (non-coherent over channels)
+ *
+ * Range: forward DFT over fast time, bin k at range k c0 Fs / (2 mu Ns).
+ * Doppler: inverse-sign DFT over blocks, so that a scatterer approaching at
+ * v (Y ~ exp(-j2pi beta l), beta = 2 fc Tb v / c0) peaks at bin d = beta L;
+ * bins are in natural order, d >= L/2 meaning d - L, velocity
+ * d_signed c0 / (2 fc Tb L).  Rectangular window, no normalisation.
+ * The peak is the largest power over all (k, d) -- over d != 0 when
+ * skip_static is set, which removes scatterers at rest (a static scatterer
+ * lands exactly in bin d = 0) -- ties going to the smallest k L + d. */
+typedef struct {
+    int32_t range_bin;    /* k, 0 .. Ns-1 */
+    int32_t doppler_bin;  /* signed d, -L/2 .. L/2-1; > 0 approaching */
+    float power;          /* power[k][d] */
+    float range_m;        /* k c0 Fs / (2 mu Ns) */
+    float velocity_mps;   /* d c0 / (2 fc Tb L) */
+    float reserved;       /* 0 */
+} rs_rd_peak;
+
+/* Range-Doppler processing of `nframes` consecutive cubes made with `plan`
+ * (its radar and output dtype; either form).  cubes: device
+ * [nframes][C][L][Ns] as written by the synthesis calls.  Outputs, all
+ * device memory, each may be NULL:
+ *   power         float32 [nframes][Ns][L]  (range-major, Doppler fastest)
+ *   doppler_time  float32 [nframes][L]      power[k_peak][.] of each frame:
+ *                                           its velocity spectrum at the peak
+ *   peaks         rs_rd_peak [nframes]
+ * Arithmetic in float32 (radix-2 FFTs in LDS, twiddles from binary64).
+ * Needs Ns and L powers of two, Ns <= 4096, L <= 1024 (else
+ * RS_E_UNSUPPORTED).  Temporary device memory (8 bytes per cube entry) is
+ * allocated and freed in stream order.
+ * Errors: RS_E_INVALID (NULL plan or cubes with nframes > 0, nframes < 0),
+ * RS_E_UNSUPPORTED, RS_E_NOMEM, RS_E_DEVICE.  nframes = 0 does nothing. */
+rs_status rs_range_doppler(rs_plan *plan, const void *cubes, int32_t nframes, int32_t skip_static,
+                           float *power, float *doppler_time, rs_rd_peak *peaks, void *hip_stream);
+
 /* --------------------------------------------------------- kernel timer -- */
 /* Per-launch timing of the main (contraction) kernel with HIP events, for
  * profiling.  A timer attached to the calling thread records an event pair

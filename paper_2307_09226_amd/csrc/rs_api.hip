@@ -33,23 +33,6 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 int round_up(int64_t v, int m) { return (int)(((v + m - 1) / m) * m); }
 
-// Restores the caller's current device on scope exit.
-struct device_guard {
-    int prev = -1;
-    rs_status st = RS_OK;
-    explicit device_guard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev && hipSetDevice(dev) != hipSuccess)
-            st = rs_fail(RS_E_DEVICE, "hipSetDevice(%d) failed", dev);
-    }
-    ~device_guard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 }  // namespace
 
 // ---------------------------------------------------------------- plans ----

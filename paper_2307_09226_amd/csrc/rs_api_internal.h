@@ -23,6 +23,23 @@ struct rs_plan {
 };
 
 rs_status rs_fail(rs_status s, const char *fmt, ...);
+
+// Makes `dev` current for a call and restores the caller's device on exit.
+struct device_guard {
+    int prev = -1;
+    rs_status st = RS_OK;
+    explicit device_guard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev && hipSetDevice(dev) != hipSuccess)
+            st = rs_fail(RS_E_DEVICE, "hipSetDevice(%d) failed", dev);
+    }
+    ~device_guard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
 void rs_choose_tiles(rs_plan *pl);
 rs_status rs_plan_chunking(const rs_plan *pl, int64_t P, int32_t *S, int32_t *chunk);
 size_t rs_partial_bytes(const rs_plan *pl, int32_t S);

@@ -65,6 +65,18 @@ class rs_session_stats(ctypes.Structure):
                 ("terms_done", ctypes.c_double)]
 
 
+class rs_rd_peak(ctypes.Structure):
+    _fields_ = [("range_bin", ctypes.c_int32), ("doppler_bin", ctypes.c_int32),
+                ("power", ctypes.c_float), ("range_m", ctypes.c_float),
+                ("velocity_mps", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+
+# numpy view of an rs_rd_peak array (same layout)
+RD_PEAK_DTYPE = np.dtype([("range_bin", np.int32), ("doppler_bin", np.int32), ("power", np.float32),
+                          ("range_m", np.float32), ("velocity_mps", np.float32),
+                          ("reserved", np.float32)])
+
+
 # Every symbol declared in include/rs.h: name -> (restype, argtypes)
 _VP = ctypes.c_void_p
 SIGNATURES = {
@@ -88,6 +100,7 @@ SIGNATURES = {
     "rs_session_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(rs_session_stats)]),
     "rs_session_destroy": (None, [_VP]),
     "rs_session_inject_failure": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "rs_range_doppler": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP]),
     "rs_kernel_timer_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP)]),
     "rs_kernel_timer_attach": (ctypes.c_int, [_VP]),
     "rs_kernel_timer_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
@@ -249,6 +262,35 @@ def rs_beat_synthesize_ws(plan: Plan, pixels: DevicePixels, cube, workspace, str
                                      _ptr(workspace) if nbytes else None, nbytes,
                                      _stream_handle(stream)))
     return cube
+
+
+def rs_range_doppler(plan: Plan, cubes, skip_static: bool = True, power=None, doppler_time=None,
+                     peaks=None, stream=None):
+    """Range-Doppler processing of cubes [F][C][L][Ns] (a single cube [C][L][Ns]
+    counts as F = 1).  power (float32 [F][Ns][L]), doppler_time (float32
+    [F][L]) and peaks (uint8 [F * 24], rs_rd_peak records) are device tensors
+    or None."""
+    nframes = 1 if cubes.dim() == 3 else int(cubes.shape[0])
+    _check(lib.rs_range_doppler(plan.handle, _ptr(cubes), nframes, 1 if skip_static else 0,
+                                _ptr(power) if power is not None else None,
+                                _ptr(doppler_time) if doppler_time is not None else None,
+                                _ptr(peaks) if peaks is not None else None,
+                                _stream_handle(stream)))
+
+
+def range_doppler(plan: Plan, cubes, skip_static: bool = True, stream=None):
+    """rs_range_doppler into new device tensors; returns (power [F][Ns][L],
+    doppler_time [F][L], peaks) with peaks a numpy record array (this
+    synchronises the stream)."""
+    import torch
+    nframes = 1 if cubes.dim() == 3 else int(cubes.shape[0])
+    r = plan.radar
+    power = torch.empty((nframes, r.Ns, r.L), dtype=torch.float32, device=cubes.device)
+    dtime = torch.empty((nframes, r.L), dtype=torch.float32, device=cubes.device)
+    peaks = torch.empty(nframes * RD_PEAK_DTYPE.itemsize, dtype=torch.uint8, device=cubes.device)
+    rs_range_doppler(plan, cubes, skip_static, power, dtime, peaks, stream)
+    pk = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=RD_PEAK_DTYPE)
+    return power, dtime, pk
 
 
 def rs_beat_synthesize_batch(plan: Plan, frames: Sequence[DevicePixels], cubes, stream=None):

@@ -18,7 +18,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("rs_cube_plan", "rs_beat_synthesize", "rs_beat_synthesize_batch",
-                 "rs_session_create", "rs_session_submit", "rs_session_poll"):
+                 "rs_session_create", "rs_session_submit", "rs_session_poll", "rs_range_doppler"):
         assert must in names
 
 
@@ -66,6 +66,7 @@ def test_invalid_plan_arguments_rejected_on_host():
     # NULL handles
     assert rs.lib.rs_beat_synthesize(None, None, None, None) == rs.RS_E_INVALID
     assert rs.lib.rs_session_submit(None, None, None, None, None) == rs.RS_E_INVALID
+    assert rs.lib.rs_range_doppler(None, None, 1, 1, None, None, None, None) == rs.RS_E_INVALID
     out = ctypes.c_size_t()
     assert rs.lib.rs_plan_workspace_bytes(None, 0, ctypes.byref(out)) == rs.RS_E_INVALID
     rs.lib.rs_plan_destroy(None)
