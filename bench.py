@@ -39,8 +39,8 @@ FLOP_PLAIN = 8         # one binary64 complex MAC
 # the kernel sources they were taken on; any change to those sources turns
 # the figure into null until the counters are taken again.
 TRAFFIC_SOURCES = ("rs_mfma.hip", "rs_device.h", "rs_internal.h")
-TRAFFIC = {"sources_sha256": "54b48807efa4aa6218420d03794e3a580b4378d10fc28e8b0022906123bfc91a",
-           "fetch_bytes": 10.80e6, "write_bytes": 67.10e6}
+TRAFFIC = {"sources_sha256": "5d2778c8752fdacb67d4658a093bec969ffa4eac388fba4c8e0f49e2e42a7bd9",
+           "fetch_bytes": 10.98e6, "write_bytes": 67.35e6}
 
 
 # Offered load of the serving leg, frozen so that latencies stay comparable
@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline single-frame measurement")
+    ap.add_argument("--legs", default="plain,batch,doppler_time,serving,cpu",
+                    help="extra legs after the headline (comma-separated subset)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
                     help="requests/s; 0 = 0.6 x the capacity measured in this run")
@@ -197,7 +199,8 @@ def main():
     torch.cuda.synchronize()
     out["parity"] = parity_sampled(radar, px, cube.cpu().numpy())
 
-    if not args.no_extras:
+    legs = set() if args.no_extras else set(args.legs.split(","))
+    if "plain" in legs:
         # ---- plain binary64 form on the same frame -------------------------------
         pplan = rs.rs_cube_plan(radar, rs.RS_FORM_FP64_DIRECT, rs.RS_C64, max_pixels=px.P)
         pcube = rs.new_cube(pplan, dev)
@@ -218,6 +221,7 @@ def main():
         out["mfma_speedup_vs_plain"] = out["value"] / out["plain_fp64"]["terms_per_s"]
         pplan.close()
 
+    if "batch" in legs:
         # ---- 64 animation frames in one persistent launch -------------------------
         frames = scenes.animation_frames(seed=3, nframes=64)
         brad = scenes.radar_batch()
@@ -242,15 +246,67 @@ def main():
         del cubes, dfr
         bplan.close()
 
-        # ---- serving loop at a fixed request rate -----------------------------------
-        if args.serving_requests > 0:
-            out["serving"] = serving(rs, scenes, dev, args)
+    if "doppler_time" in legs:
+        # ---- walking circle: 100 CPIs, range-Doppler maps, Doppler-time ------------
+        out["doppler_time"] = doppler_time_leg(rs, scenes, dev, timer)
 
+    if "serving" in legs and args.serving_requests > 0:
+        # ---- serving loop at a fixed request rate -----------------------------------
+        out["serving"] = serving(rs, scenes, dev, args)
+
+    if "cpu" in legs:
         # ---- CPU oracle on the host cores -------------------------------------------
         out["cpu_baseline"] = cpu_baseline(radar, px, args.cpu_seconds)
     timer.close()
     plan.close()
     print(json.dumps(out), flush=True)
+
+
+def doppler_time_leg(rs, scenes, dev, timer):
+    """The walking-circle scenario (3 m radius, 100 frames at 24 Hz): the
+    100 cubes in one batched launch, then range-Doppler maps of all of them
+    and the max-power velocity per CPI against the pedestrian's radial
+    velocity (E_velo)."""
+    import torch
+    radar = scenes.radar_frame()
+    cw = scenes.circle_walk()
+    F = len(cw.frames)
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64,
+                           max_pixels=max(f.P for f in cw.frames))
+    dfr = [rs.DevicePixels.from_host(f, dev) for f in cw.frames]
+    cubes = rs.new_cube(plan, dev, count=F)
+    terms = sum(f.P for f in cw.frames) * radar.C * radar.Ns * radar.L
+    with timer:
+        swall, _ = timed_steps(lambda: rs.rs_beat_synthesize_batch(plan, dfr, cubes), 3, 1)
+    sk = timer.read()
+    power = torch.empty((F, radar.Ns, radar.L), dtype=torch.float32, device=dev)
+    dtime = torch.empty((F, radar.L), dtype=torch.float32, device=dev)
+    peaks = torch.empty(F * rs.RD_PEAK_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    rwall, rper = timed_steps(lambda: rs.rs_range_doppler(plan, cubes, True, power, dtime, peaks), 10, 2)
+    torch.cuda.synchronize()
+    pk = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=rs.RD_PEAK_DTYPE)
+    v_est = pk["velocity_mps"].astype(np.float64)
+    err = np.abs(v_est - cw.v_radial)
+    rd_ms = rwall * 1e3 / 10
+    # algorithmic bytes: every cube entry read once (complex64), the power
+    # map written once (float32)
+    rd_bytes = F * radar.C * radar.L * radar.Ns * 8 + F * radar.Ns * radar.L * 4
+    plan.close()
+    return {"workload": f"walking circle, radius 3 m, {F} frames at 24 Hz (4.52 m/s), room 12 x 10 m, "
+                        "256x256 px, 3 Tx x 4 Rx, Ns=256, L=128",
+            "pixels_total": sum(f.P for f in cw.frames), "terms": terms,
+            "synth_ms": swall * 1e3 / 3, "synth_terms_per_s": terms / (swall / 3),
+            "synth_kernel_ms": float(np.mean(sk[1:])) if len(sk) > 1 else None,
+            "rd_ms": rd_ms, "rd_p50_ms": pct(rper, 50),
+            "rd_algorithmic_bytes": rd_bytes,
+            "rd_roofline": {"bound": "hbm", "achieved": rd_bytes / (rd_ms * 1e-3) / 1e9, "peak": 8000.0,
+                            "unit": "GB/s", "frac": rd_bytes / (rd_ms * 1e-3) / 8e12},
+            "E_velo_mps": float(np.mean(err)), "max_abs_error_mps": float(err.max()),
+            "doppler_bin_mps": float(radar.c0 / (2 * radar.fc * radar.Tb * radar.L)),
+            "corr_v_est_v_true": float(np.corrcoef(v_est, cw.v_radial)[0, 1]),
+            "paper_E_velo_mps": 1.3,
+            "v_est": [round(float(v), 3) for v in v_est],
+            "v_true": [round(float(v), 3) for v in cw.v_radial]}
 
 
 def copy_probe(mib):
