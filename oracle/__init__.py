@@ -44,7 +44,7 @@ class _Radar(ctypes.Structure):
                 ("L", ctypes.c_int32), ("fc", ctypes.c_double), ("mu", ctypes.c_double),
                 ("Fs", ctypes.c_double), ("Tb", ctypes.c_double), ("c0", ctypes.c_double),
                 ("tx", ctypes.POINTER(ctypes.c_double)), ("rx", ctypes.POINTER(ctypes.c_double)),
-                ("carrier_phase", ctypes.c_int32)]
+                ("carrier_phase", ctypes.c_int32), ("model", ctypes.c_int32)]
 
 
 class _Pixels(ctypes.Structure):
@@ -90,7 +90,7 @@ class Oracle:
         rx = np.ascontiguousarray(r.rx, dtype=np.float64).reshape(r.N, 3)
         s = _Radar(int(r.M), int(r.N), int(r.Ns), int(r.L), float(r.fc), float(r.mu),
                    float(r.Fs), float(r.Tb), float(r.c0), _f64p(tx), _f64p(rx),
-                   int(r.carrier_phase))
+                   int(r.carrier_phase), int(getattr(r, "model", 0)))
         return s, (tx, rx)
 
     @staticmethod

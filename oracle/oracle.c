@@ -30,6 +30,23 @@
  *   phi = psi_f + th_f - ph_f wrapped to [-1/2, 1/2)
  *   term = (double)a * (cos(2 pi phi), sin(2 pi phi)), summed in increasing p.
  *
+ * Signal-model variants (bit flags in orc_radar.model; 0 = the model above).
+ * Each changes only the per-(pixel, channel) arguments psi and b, evaluated
+ * in binary64 in this order:
+ *   FAR_FIELD (1)   eq. (2) read literally: the beat frequency uses the
+ *                   range from the array origin Rp = |x| and the carrier
+ *                   phase its first-order expansion over the array,
+ *                   Rc = Rp - u.(tx_m + rx_r)/2 with u = x/Rp (eq. (2)'s
+ *                   angle-of-arrival term); psi = Rc Kc, b = Rp Kb
+ *   RVP (8)         residual video phase of the dechirped signal,
+ *                   -mu tau^2 / 2 with tau = 2 R / c0:  psi -= (R R) Krvp,
+ *                   Krvp = (2 mu)/(c0 c0), R the beat range
+ *   TDM_SLOT (2)    Tx m transmits in slot m of each block, at l Tb + m Tb/M:
+ *                   psi -= beta (m / M)
+ *   INTRA_CHIRP (4) Doppler shift within the chirp, with the sign of the
+ *                   slow-time term (the echo delay shrinks as an approaching
+ *                   scatterer closes in): b -= v Kf, Kf = (2 fc)/(c0 Fs)
+ *
  * Output layout: interleaved (re, im) doubles, [C][L][Ns] row-major, n fastest.
  */
 #include <math.h>
@@ -45,7 +62,10 @@ typedef struct {
     const double *tx; /* [M][3] */
     const double *rx; /* [N][3] */
     int32_t carrier_phase;
+    int32_t model;    /* signal-model variant flags, see above */
 } orc_radar;
+
+enum { ORC_FAR_FIELD = 1, ORC_TDM_SLOT = 2, ORC_INTRA_CHIRP = 4, ORC_RVP = 8, ORC_MODEL_ALL = 15 };
 
 typedef struct {
     int64_t P;
@@ -65,11 +85,17 @@ static void orc_set_threads(int nthreads)
 }
 
 /* Plan constants of the recipe. */
-static void constants(const orc_radar *r, double *Kc, double *Kb, double *Kd)
+typedef struct {
+    double Kc, Kb, Kd, Kf, Krvp;
+} orc_consts;
+
+static void constants(const orc_radar *r, orc_consts *k)
 {
-    *Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;
-    *Kb = (2.0 * r->mu) / (r->c0 * r->Fs);
-    *Kd = ((2.0 * r->fc) * r->Tb) / r->c0;
+    k->Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;
+    k->Kb = (2.0 * r->mu) / (r->c0 * r->Fs);
+    k->Kd = ((2.0 * r->fc) * r->Tb) / r->c0;
+    k->Kf = (2.0 * r->fc) / (r->c0 * r->Fs);
+    k->Krvp = (2.0 * r->mu) / (r->c0 * r->c0);
 }
 
 /* Euclidean distance from a float32 pixel position to an antenna. */
@@ -81,24 +107,47 @@ static double distance(float x, float y, float z, const double *ant)
     return sqrt((dx * dx + dy * dy) + dz * dz);
 }
 
-/* Half bistatic path length of pixel p for channel c = m*N + r. */
-static double half_path(const orc_radar *r, const orc_pixels *px, int64_t p, int c)
+/* Phase arguments of pixel p in channel c = m*N + r (Sec. II, eq. (1)):
+ * psi the carrier phase of sigma (cycles, not reduced), b the beat frequency
+ * (cycles per fast-time sample), beta the Doppler phase per block (cycles).
+ * Without variant flags R = (|x - tx_m| + |x - rx_r|) / 2, psi = R Kc,
+ * b = R Kb, beta = v Kd. */
+static void chan_args(const orc_radar *r, const orc_consts *k, const orc_pixels *px, int64_t p, int c,
+                      double *psi, double *b, double *beta)
 {
     int m = c / r->N, rr = c % r->N;
-    double rt = distance(px->x[p], px->y[p], px->z[p], r->tx + 3 * m);
-    double rv = distance(px->x[p], px->y[p], px->z[p], r->rx + 3 * rr);
-    return 0.5 * (rt + rv);
+    const double *tx = r->tx + 3 * m, *rx = r->rx + 3 * rr;
+    double v = (double)px->vr[p];
+    double Rc, Rb;
+    if (r->model & ORC_FAR_FIELD) {
+        double x = (double)px->x[p], y = (double)px->y[p], z = (double)px->z[p];
+        double Rp = sqrt((x * x + y * y) + z * z);
+        double ux = x / Rp, uy = y / Rp, uz = z / Rp;
+        double s = 0.5 * ((ux * (tx[0] + rx[0]) + uy * (tx[1] + rx[1])) + uz * (tx[2] + rx[2]));
+        Rc = Rp - s;
+        Rb = Rp;
+    } else {
+        double rt = distance(px->x[p], px->y[p], px->z[p], tx);
+        double rv = distance(px->x[p], px->y[p], px->z[p], rx);
+        Rc = 0.5 * (rt + rv);
+        Rb = Rc;
+    }
+    *beta = v * k->Kd;
+    *psi = Rc * k->Kc;
+    *b = Rb * k->Kb;
+    if (r->model & ORC_RVP) *psi = *psi - (Rb * Rb) * k->Krvp;
+    if (r->model & ORC_TDM_SLOT) *psi = *psi - *beta * ((double)m / (double)r->M);
+    if (r->model & ORC_INTRA_CHIRP) *b = *b - v * k->Kf;
 }
 
 static double frac(double v) { return v - floor(v); }
 
 /* One term a * exp(j 2 pi (psi + b n - beta l)) by the fixed recipe. */
-static void term(double R, double a, double v, int n, int l,
-                 double Kc, double Kb, double Kd, double *re, double *im)
+static void term(double psi, double b, double beta, double a, int n, int l, double *re, double *im)
 {
-    double psi_f = frac(R * Kc);
-    double th_f = frac((R * Kb) * (double)n);
-    double ph_f = frac((v * Kd) * (double)l);
+    double psi_f = frac(psi);
+    double th_f = frac(b * (double)n);
+    double ph_f = frac(beta * (double)l);
     double phi = (psi_f + th_f) - ph_f;
     phi = phi - floor(phi + 0.5);
     double ang = TWO_PI * phi;
@@ -114,6 +163,7 @@ static int valid(const orc_radar *r, const orc_pixels *px)
     if (px->P < 0) return 0;
     if (px->P > 0 && (!px->x || !px->y || !px->z || !px->amp || !px->vr)) return 0;
     if (!r->tx || !r->rx) return 0;
+    if (r->model < 0 || (r->model & ~ORC_MODEL_ALL)) return 0;
     return 1;
 }
 
@@ -121,8 +171,8 @@ static int valid(const orc_radar *r, const orc_pixels *px)
 int orc_cube(const orc_radar *r, const orc_pixels *px, double *out, int nthreads)
 {
     if (!valid(r, px) || !out) return 1;
-    double Kc, Kb, Kd;
-    constants(r, &Kc, &Kb, &Kd);
+    orc_consts k;
+    constants(r, &k);
     const int C = r->M * r->N, L = r->L, Ns = r->Ns;
     const int64_t P = px->P;
     orc_set_threads(nthreads);
@@ -132,11 +182,12 @@ int orc_cube(const orc_radar *r, const orc_pixels *px, double *out, int nthreads
         double *o = out + 2 * row * Ns;
         for (int n = 0; n < Ns; ++n) { o[2 * n] = 0.0; o[2 * n + 1] = 0.0; }
         for (int64_t p = 0; p < P; ++p) {
-            double R = half_path(r, px, p, c);
-            double a = (double)px->amp[p], v = (double)px->vr[p];
+            double psi, b, beta;
+            chan_args(r, &k, px, p, c, &psi, &b, &beta);
+            double a = (double)px->amp[p];
             for (int n = 0; n < Ns; ++n) {
                 double re, im;
-                term(R, a, v, n, l, Kc, Kb, Kd, &re, &im);
+                term(psi, b, beta, a, n, l, &re, &im);
                 o[2 * n] += re;
                 o[2 * n + 1] += im;
             }
@@ -155,16 +206,17 @@ int orc_entries(const orc_radar *r, const orc_pixels *px, int64_t K,
     for (int64_t k = 0; k < K; ++k)
         if (cs[k] < 0 || cs[k] >= C || ls[k] < 0 || ls[k] >= r->L || ns[k] < 0 || ns[k] >= r->Ns)
             return 1;
-    double Kc, Kb, Kd;
-    constants(r, &Kc, &Kb, &Kd);
+    orc_consts kk;
+    constants(r, &kk);
     orc_set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t k = 0; k < K; ++k) {
         double sre = 0.0, sim = 0.0;
         for (int64_t p = 0; p < px->P; ++p) {
-            double R = half_path(r, px, p, cs[k]);
+            double psi, b, beta;
+            chan_args(r, &kk, px, p, cs[k], &psi, &b, &beta);
             double re, im;
-            term(R, (double)px->amp[p], (double)px->vr[p], ns[k], ls[k], Kc, Kb, Kd, &re, &im);
+            term(psi, b, beta, (double)px->amp[p], ns[k], ls[k], &re, &im);
             sre += re;
             sim += im;
         }
@@ -201,8 +253,8 @@ static void geom(int N, double x, double *re, double *im)
 int orc_marginal_n(const orc_radar *r, const orc_pixels *px, double *out, int nthreads)
 {
     if (!valid(r, px) || !out) return 1;
-    double Kc, Kb, Kd;
-    constants(r, &Kc, &Kb, &Kd);
+    orc_consts k;
+    constants(r, &k);
     const int C = r->M * r->N, L = r->L;
     orc_set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -210,9 +262,9 @@ int orc_marginal_n(const orc_radar *r, const orc_pixels *px, double *out, int nt
         int c = (int)(row / L), l = (int)(row % L);
         double sre = 0.0, sim = 0.0;
         for (int64_t p = 0; p < px->P; ++p) {
-            double R = half_path(r, px, p, c);
-            double b = R * Kb;
-            double ph = frac(R * Kc) - frac(((double)px->vr[p] * Kd) * (double)l);
+            double psi, b, beta;
+            chan_args(r, &k, px, p, c, &psi, &b, &beta);
+            double ph = frac(psi) - frac(beta * (double)l);
             double gr, gi;
             geom(r->Ns, b, &gr, &gi);
             double cr = cos(TWO_PI * ph), ci = sin(TWO_PI * ph);
@@ -231,8 +283,8 @@ int orc_marginal_n(const orc_radar *r, const orc_pixels *px, double *out, int nt
 int orc_marginal_l(const orc_radar *r, const orc_pixels *px, double *out, int nthreads)
 {
     if (!valid(r, px) || !out) return 1;
-    double Kc, Kb, Kd;
-    constants(r, &Kc, &Kb, &Kd);
+    orc_consts k;
+    constants(r, &k);
     const int C = r->M * r->N, Ns = r->Ns;
     orc_set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -240,9 +292,9 @@ int orc_marginal_l(const orc_radar *r, const orc_pixels *px, double *out, int nt
         int c = (int)(row / Ns), n = (int)(row % Ns);
         double sre = 0.0, sim = 0.0;
         for (int64_t p = 0; p < px->P; ++p) {
-            double R = half_path(r, px, p, c);
-            double beta = (double)px->vr[p] * Kd;
-            double ph = frac(R * Kc) + frac((R * Kb) * (double)n);
+            double psi, b, beta;
+            chan_args(r, &k, px, p, c, &psi, &b, &beta);
+            double ph = frac(psi) + frac(b * (double)n);
             double gr, gi;
             geom(r->L, -beta, &gr, &gi);
             double cr = cos(TWO_PI * ph), ci = sin(TWO_PI * ph);

@@ -54,6 +54,8 @@ class Radar:
     Tb block period [s] (one block holds M chirps), c0 [m/s].
     tx, rx: antenna positions [M][3], [N][3] in metres (float64).
     carrier_phase: 1 puts the exact carrier phase 2 fc R / c0 into sigma.
+    model: signal-model variant flags (1 far field as eq. (2), 2 Tx slot
+    timing, 4 Doppler within the chirp, 8 residual video phase).
     """
 
     M: int
@@ -68,6 +70,7 @@ class Radar:
     rx: np.ndarray
     c0: float = C0
     carrier_phase: int = 1
+    model: int = 0
 
     @property
     def C(self) -> int:

@@ -258,7 +258,117 @@ def pin_brute_exact_no_carrier(o):
     assert np.all(np.abs(o.cube(r, px) - ref) <= bound)
 
 
-ALL_PINS = [pin_empty_scene, pin_single_scatterer_closed_form, pin_range_and_doppler_peaks,
+# ----------------------------------------------------------------------------
+# Signal-model variants (flags: 1 far field, 2 Tx slot timing, 4 Doppler
+# within the chirp, 8 residual video phase)
+def _with_model(r, model):
+    import dataclasses
+    return dataclasses.replace(r, model=model)
+
+
+def pin_model_zero_is_default(o):
+    """Variants that vanish for a static scene or a single Tx leave the cube
+    bitwise unchanged: slot timing with M = 1 or v = 0, intra-chirp Doppler
+    with v = 0."""
+    r = scenes.radar_for(1, 3, 8, 4, Fs=5e6, Tb=80e-6)
+    px = scenes.tiny_scene(51, 5)
+    base = o.cube(r, px)
+    assert np.array_equal(o.cube(_with_model(r, 2), px), base)
+    r2 = scenes.radar_for(2, 2, 8, 4, Fs=5e6, Tb=80e-6)
+    px0 = scenes.tiny_scene(52, 5, vmax=0.0)
+    base2 = o.cube(r2, px0)
+    assert np.array_equal(o.cube(_with_model(r2, 2 | 4), px0), base2)
+
+
+def pin_slot_timing_alias(o):
+    """Tx m fires at l Tb + m Tb / M.  One extra Doppler cycle per block
+    (v + c0 / (2 fc Tb)) then turns channel m by exactly exp(-j2pi m / M),
+    and M extra cycles per block leave every channel unchanged."""
+    r = _with_model(scenes.radar_for(3, 2, 8, 4, Fs=5e6, Tb=120e-6), 2)
+    v0 = 1.3
+    dv = r.c0 / (2 * r.fc * r.Tb)
+    Ya = o.cube(r, _one_pixel(0.4, 3.1, 0.2, 1.0, v0))
+    Yb = o.cube(r, _one_pixel(0.4, 3.1, 0.2, 1.0, np.float32(v0 + dv)))
+    Yc = o.cube(r, _one_pixel(0.4, 3.1, 0.2, 1.0, np.float32(v0 + r.M * dv)))
+    vb = float(np.float32(v0 + dv)) - float(np.float32(v0))
+    vc = float(np.float32(v0 + r.M * dv)) - float(np.float32(v0))
+    for c in range(r.C):
+        m = c // r.N
+        for l in range(r.L):
+            # the float32 velocities are off the exact alias by a few ulp:
+            # remove that residual Doppler before comparing
+            res_b = np.exp(-2j * np.pi * ((vb - dv) * 2 * r.fc * r.Tb / r.c0) * (l + m / r.M))
+            res_c = np.exp(-2j * np.pi * ((vc - r.M * dv) * 2 * r.fc * r.Tb / r.c0) * (l + m / r.M))
+            want_b = Ya[c, l] * np.exp(-2j * np.pi * m / r.M) * res_b
+            assert np.max(np.abs(Yb[c, l] - want_b)) < 1e-6, (c, l)
+            assert np.max(np.abs(Yc[c, l] - Ya[c, l] * res_c)) < 1e-6, (c, l)
+
+
+def pin_dechirp_physics(o):
+    """The dechirped echo of one moving scatterer written from the FMCW
+    chirp itself: s(t) = exp(j2pi(fc t + mu t^2 / 2)), echo delay
+    tau(t) = 2 (R0 - v t) / c0, y = s(t) conj(s(t - tau)) over the first
+    chirp.  With the residual-video-phase and intra-chirp-Doppler variants
+    the cube's l = 0 row follows y to within the second-order terms the
+    model leaves out (-2 mu v t^2 / c0, a few thousandths of a cycle here);
+    without them it does not."""
+    z = np.zeros((1, 3))
+    r = scenes.Radar(M=1, N=1, Ns=64, L=2, fc=77e9, mu=30e12, Fs=5e6, Tb=80e-6, tx=z, rx=z.copy())
+    px = _one_pixel(1.2, 6.5, 0.3, 1.0, 100.0)
+    with mp.workdps(40):
+        pos = [mp.mpf(float(v)) for v in (px.x[0], px.y[0], px.z[0])]
+        R0 = mp.sqrt(sum(q * q for q in pos))
+        v = mp.mpf(float(px.vr[0]))
+        want = []
+        for n in range(r.Ns):
+            t = mp.mpf(n) / r.Fs
+            tau = 2 * (R0 - v * t) / r.c0
+            ph = (r.fc * t + r.mu * t * t / 2) - (r.fc * (t - tau) + r.mu * (t - tau) ** 2 / 2)
+            want.append(complex(mp.expj(2 * mp.pi * ph)))
+    want = np.array(want)
+    full = o.cube(_with_model(r, 4 | 8), px)[0, 0]
+    cyc = np.abs(np.angle(full / want)) / (2 * np.pi)
+    assert cyc.max() < 0.01, cyc.max()
+    plain = o.cube(r, px)[0, 0]
+    assert (np.abs(np.angle(plain / want)) / (2 * np.pi)).max() > 0.02
+
+
+def pin_far_field_model(o):
+    """Far-field variant (eq. (2) read literally): across the virtual ULA the
+    channels differ at n = l = 0 by exactly eq. (2)'s angle term
+    exp(-j2pi c (lambda/2) u_x / lambda) at any distance; along fast time the
+    phase advances by 2 mu |x| / (c0 Fs) per sample, the range from the array
+    origin; and the variant approaches the exact model as 1/distance."""
+    r = _with_model(scenes.radar_for(3, 4, 16, 2, Fs=10e6, Tb=120e-6), 1)
+    lam = r.wavelength
+    for dist in (2.0, 40.0):
+        az, el = math.radians(-25.0), math.radians(8.0)
+        u = np.array([math.cos(el) * math.sin(az), math.cos(el) * math.cos(az), math.sin(el)])
+        px = _one_pixel(*(dist * u), 1.0, 0.0)
+        Y = o.cube(r, px)
+        x = np.array([float(px.x[0]), float(px.y[0]), float(px.z[0])])
+        Rp = np.linalg.norm(x)
+        ux = x[0] / Rp
+        for c in range(r.C):
+            got = Y[c, 0, 0] / Y[0, 0, 0]
+            want = np.exp(-2j * np.pi * c * (lam / 2) * ux / lam)
+            assert abs(np.angle(got / want)) < 1e-8, (dist, c)
+        b = 2 * r.mu * Rp / (r.c0 * r.Fs)
+        got = Y[5, 0, 1:] / Y[5, 0, :-1]
+        assert np.max(np.abs(np.angle(got / np.exp(2j * np.pi * b)))) < 1e-8
+    # convergence to the exact model
+    errs = []
+    rr = scenes.radar_for(3, 4, 16, 2, Fs=10e6, Tb=120e-6, carrier_phase=1)
+    for dist in (20.0, 2000.0):
+        u = np.array([0.3, 0.9, 0.1]) / np.linalg.norm([0.3, 0.9, 0.1])
+        px = _one_pixel(*(dist * u), 1.0, 0.0)
+        d = o.cube(_with_model(rr, 1), px)[:, 0, 0] / o.cube(rr, px)[:, 0, 0]
+        errs.append(np.max(np.abs(np.angle(d))))
+    assert errs[1] < errs[0] / 30, errs
+
+
+ALL_PINS = [pin_model_zero_is_default, pin_slot_timing_alias, pin_dechirp_physics,
+            pin_far_field_model, pin_empty_scene, pin_single_scatterer_closed_form, pin_range_and_doppler_peaks,
             pin_marginals, pin_linearity, pin_static_scene_slices, pin_doppler_alias,
             pin_eq1_per_rx, pin_far_field, pin_entries_match_cube, pin_brute_recipe,
             pin_brute_exact, pin_brute_exact_no_carrier]

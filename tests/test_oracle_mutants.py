@@ -11,33 +11,45 @@ import pins
 # (name, original text, replacement): a dropped term, a wrong sign, a wrong
 # or transposed index, a wrong scale, a mistake in a closed form.
 MUTANTS = [
-    ("rx_ignored", "return 0.5 * (rt + rv);", "return 0.5 * (rt + rt);"),
-    ("full_path_not_half", "return 0.5 * (rt + rv);", "return (rt + rv);"),
+    ("rx_ignored", "Rc = 0.5 * (rt + rv);", "Rc = 0.5 * (rt + rt);"),
+    ("full_path_not_half", "Rc = 0.5 * (rt + rv);", "Rc = (rt + rv);"),
     ("doppler_sign", "double phi = (psi_f + th_f) - ph_f;", "double phi = (psi_f + th_f) + ph_f;"),
     ("beat_sign", "double phi = (psi_f + th_f) - ph_f;", "double phi = (psi_f - th_f) - ph_f;"),
     ("channel_transposed", "int m = c / r->N, rr = c % r->N;", "int m = c % r->M, rr = c / r->M;"),
-    ("beat_factor_two", "*Kb = (2.0 * r->mu) / (r->c0 * r->Fs);", "*Kb = (r->mu) / (r->c0 * r->Fs);"),
-    ("carrier_dropped", "*Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;", "*Kc = 0.0;"),
-    ("carrier_always", "*Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;",
-     "*Kc = (2.0 * r->fc) / r->c0;"),
-    ("doppler_no_Tb", "*Kd = ((2.0 * r->fc) * r->Tb) / r->c0;", "*Kd = (2.0 * r->fc) / r->c0;"),
-    ("n_off_by_one", "term(R, a, v, n, l, Kc, Kb, Kd, &re, &im);",
-     "term(R, a, v, n + 1, l, Kc, Kb, Kd, &re, &im);"),
-    ("l_off_by_one", "term(R, a, v, n, l, Kc, Kb, Kd, &re, &im);",
-     "term(R, a, v, n, l + 1, Kc, Kb, Kd, &re, &im);"),
-    ("n_l_swapped_in_phase", "double th_f = frac((R * Kb) * (double)n);",
-     "double th_f = frac((R * Kb) * (double)l);"),
+    ("beat_factor_two", "k->Kb = (2.0 * r->mu) / (r->c0 * r->Fs);", "k->Kb = (r->mu) / (r->c0 * r->Fs);"),
+    ("carrier_dropped", "k->Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;", "k->Kc = 0.0;"),
+    ("carrier_always", "k->Kc = r->carrier_phase ? (2.0 * r->fc) / r->c0 : 0.0;",
+     "k->Kc = (2.0 * r->fc) / r->c0;"),
+    ("doppler_no_Tb", "k->Kd = ((2.0 * r->fc) * r->Tb) / r->c0;", "k->Kd = (2.0 * r->fc) / r->c0;"),
+    ("n_off_by_one", "term(psi, b, beta, a, n, l, &re, &im);", "term(psi, b, beta, a, n + 1, l, &re, &im);"),
+    ("l_off_by_one", "term(psi, b, beta, a, n, l, &re, &im);", "term(psi, b, beta, a, n, l + 1, &re, &im);"),
+    ("n_l_swapped_in_phase", "double th_f = frac(b * (double)n);", "double th_f = frac(b * (double)l);"),
     ("amp_squared", "*re = a * cos(ang);\n    *im = a * sin(ang);",
      "*re = a * a * cos(ang);\n    *im = a * a * sin(ang);"),
     ("conjugate_output", "o[2 * n + 1] += im;", "o[2 * n + 1] -= im;"),
     ("dz_uses_y", "double dz = (double)z - ant[2];", "double dz = (double)z - ant[1];"),
     ("dropped_dz", "return sqrt((dx * dx + dy * dy) + dz * dz);", "return sqrt(dx * dx + dy * dy);"),
     ("first_pixel_skipped", "for (int64_t p = 0; p < P; ++p) {", "for (int64_t p = 1; p < P; ++p) {"),
-    ("entries_n_l_swapped", "ns[k], ls[k], Kc, Kb, Kd", "ls[k] % r->Ns, ns[k] % r->L, Kc, Kb, Kd"),
+    ("entries_n_l_swapped", "(double)px->amp[p], ns[k], ls[k], &re, &im);",
+     "(double)px->amp[p], ls[k] % r->Ns, ns[k] % r->L, &re, &im);"),
     ("marginal_l_sign", "geom(r->L, -beta, &gr, &gi);", "geom(r->L, beta, &gr, &gi);"),
     ("marginal_n_length", "geom(r->Ns, b, &gr, &gi);", "geom(r->Ns - 1, b, &gr, &gi);"),
     ("geom_phase_half", "double ang = PI * fmod((double)(N - 1) * xr, 2.0);",
      "double ang = PI * fmod((double)N * xr, 2.0);"),
+    # signal-model variants
+    ("slot_sign", "*psi = *psi - *beta * ((double)m / (double)r->M);",
+     "*psi = *psi + *beta * ((double)m / (double)r->M);"),
+    ("slot_whole_blocks", "*psi = *psi - *beta * ((double)m / (double)r->M);", "*psi = *psi - *beta * (double)m;"),
+    ("slot_by_rx", "*psi = *psi - *beta * ((double)m / (double)r->M);",
+     "*psi = *psi - *beta * ((double)rr / (double)r->M);"),
+    ("intra_sign", "*b = *b - v * k->Kf;", "*b = *b + v * k->Kf;"),
+    ("intra_uses_beat_constant", "*b = *b - v * k->Kf;", "*b = *b - v * k->Kb;"),
+    ("rvp_sign", "*psi = *psi - (Rb * Rb) * k->Krvp;", "*psi = *psi + (Rb * Rb) * k->Krvp;"),
+    ("rvp_factor", "k->Krvp = (2.0 * r->mu) / (r->c0 * r->c0);", "k->Krvp = (r->mu) / (r->c0 * r->c0);"),
+    ("ff_beat_uses_carrier_range", "Rb = Rp;", "Rb = Rc;"),
+    ("ff_no_half", "double s = 0.5 * ((ux", "double s = ((ux"),
+    ("ff_sign", "Rc = Rp - s;", "Rc = Rp + s;"),
+    ("ff_ignores_rx", "uz * (tx[2] + rx[2]));", "uz * (tx[2] + rx[2])) + 0.5 * ((ux * (tx[0] - rx[0]) + uy * (tx[1] - rx[1])) + uz * (tx[2] - rx[2]));"),
 ]
 
 
