@@ -72,6 +72,32 @@ typedef enum {
 typedef enum { RS_FORM_FP64_DIRECT = 0, RS_FORM_MFMA_SPLIT16 = 1 } rs_form;
 typedef enum { RS_C64 = 0, RS_C128 = 1 } rs_dtype; /* interleaved (re, im) */
 
+/* Signal-model variants (bit flags, rs_radar.model; 0 = the model above).
+ * Each changes only the per-(pixel, channel) phase arguments psi and b, in
+ * binary64, in this order:
+ *   RS_MODEL_FAR_FIELD    eq. (2) read literally: the beat frequency uses
+ *                         the range from the array origin Rp = |x| and the
+ *                         carrier phase its first-order expansion over the
+ *                         array, Rc = Rp - u.(tx_m + rx_r)/2 with u = x/Rp
+ *                         (eq. (2)'s angle-of-arrival term):
+ *                         psi = Rc Kc, b = Rp Kb.  Pixels must not sit at
+ *                         the origin.
+ *   RS_MODEL_RVP          residual video phase of the dechirped echo,
+ *                         -mu tau^2 / 2 with tau = 2 R / c0:
+ *                         psi -= R^2 (2 mu / c0^2), R the beat range
+ *   RS_MODEL_TDM_SLOT     Tx m transmits in slot m of each block, at
+ *                         l Tb + m Tb / M (eq. (1) uses l Tb for all Tx):
+ *                         psi -= beta m / M
+ *   RS_MODEL_INTRA_CHIRP  Doppler shift within the chirp, with the sign of
+ *                         the slow-time term: b -= v (2 fc / (c0 Fs))
+ * Range migration over the CPI is not modelled by any variant. */
+typedef enum {
+    RS_MODEL_FAR_FIELD = 1,
+    RS_MODEL_TDM_SLOT = 2,
+    RS_MODEL_INTRA_CHIRP = 4,
+    RS_MODEL_RVP = 8
+} rs_model_flags;
+
 /* eq. (1) signal model, SI units.  tx_xyz / rx_xyz are HOST arrays
  * [M][3] / [N][3] of antenna positions in metres; they are copied by
  * rs_cube_plan and may be freed on return. */
@@ -80,6 +106,7 @@ typedef struct {
     double fc, mu, Fs, Tb, c0; /* Hz, Hz/s, Hz, s, m/s (Fs, Tb, c0 > 0)        */
     const double *tx_xyz, *rx_xyz;
     int32_t carrier_phase;   /* 1: sigma = a exp(j 2 pi 2 fc R / c0); 0: a     */
+    int32_t model;           /* rs_model_flags, 0 = eq. (1) as above            */
 } rs_radar;
 
 /* One frame of rendered pixels, caller-owned DEVICE pointers, float32 SoA. */
@@ -97,6 +124,7 @@ typedef struct rs_session rs_session;
  * the current HIP device and choose the tile configuration.  max_pixels
  * bounds P for every later call on this plan (>= 0).
  * Errors: RS_E_INVALID (M, N, Ns or L < 1, M*N*L*Ns > 2^31, Fs, Tb or c0 <= 0,
+ * unknown model flags,
  * any non-finite parameter, NULL tx/rx, bad form or dtype, max_pixels < 0),
  * RS_E_NOMEM, RS_E_DEVICE.  On success *out owns device memory until
  * rs_plan_destroy.  A plan is immutable and may be used from several threads

@@ -92,6 +92,9 @@ rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *par
     j.Kc = pl->Kc;
     j.Kb = pl->Kb;
     j.Kd = pl->Kd;
+    j.Kf = pl->Kf;
+    j.Krvp = pl->Krvp;
+    j.model = pl->model;
     j.M = pl->M;
     j.N = pl->N;
     j.Ns = pl->Ns;
@@ -238,6 +241,8 @@ extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtyp
     if (form != RS_FORM_FP64_DIRECT && form != RS_FORM_MFMA_SPLIT16)
         return rs_fail(RS_E_INVALID, "unknown form");
     if (dtype != RS_C64 && dtype != RS_C128) return rs_fail(RS_E_INVALID, "unknown dtype");
+    if (r->model < 0 || (r->model & ~(RS_MODEL_FAR_FIELD | RS_MODEL_TDM_SLOT | RS_MODEL_INTRA_CHIRP | RS_MODEL_RVP)))
+        return rs_fail(RS_E_INVALID, "unknown model flags 0x%x", (unsigned)r->model);
     if (max_pixels < 0) return rs_fail(RS_E_INVALID, "max_pixels < 0");
     if (max_pixels > ((int64_t)1 << 40)) return rs_fail(RS_E_INVALID, "max_pixels too large");
 
@@ -271,6 +276,9 @@ extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtyp
     pl->Kc = pl->carrier ? (2.0 * r->fc) / r->c0 : 0.0;
     pl->Kb = (2.0 * r->mu) / (r->c0 * r->Fs);
     pl->Kd = ((2.0 * r->fc) * r->Tb) / r->c0;
+    pl->Kf = (2.0 * r->fc) / (r->c0 * r->Fs);
+    pl->Krvp = (2.0 * r->mu) / (r->c0 * r->c0);
+    pl->model = r->model;
     pl->form = form;
     pl->dtype = dtype;
     pl->max_pixels = max_pixels;
@@ -371,11 +379,11 @@ extern "C" rs_status rs_plan_describe(const rs_plan *pl, int64_t P, char *buf, s
     snprintf(buf, len,
              "{\"form\": \"%s\", \"dtype\": \"%s\", \"C\": %d, \"Ns\": %d, \"L\": %d, "
              "\"tile_n\": %d, \"tile_l\": %d, \"wave_rows\": %d, \"waves\": %d, \"n_tiles\": %d, \"l_tiles\": %d, "
-             "\"chunks\": %d, \"chunk_pixels\": %d, \"items\": %lld, \"cus\": %d}",
+             "\"chunks\": %d, \"chunk_pixels\": %d, \"items\": %lld, \"cus\": %d, \"model\": %d}",
              pl->form == RS_FORM_FP64_DIRECT ? "fp64_direct" : "mfma_split16",
              pl->dtype == RS_C128 ? "complex128" : "complex64", pl->C, pl->Ns, pl->L, pl->tn,
              pl->tl, pl->wn, pl->form == RS_FORM_FP64_DIRECT ? 4 : pl->nw, pl->n_tiles, pl->l_tiles, S, chunk,
-             (long long)S * pl->C * pl->n_tiles * pl->l_tiles, pl->ncu);
+             (long long)S * pl->C * pl->n_tiles * pl->l_tiles, pl->ncu, pl->model);
     return RS_OK;
 }
 

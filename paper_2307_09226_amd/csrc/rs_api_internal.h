@@ -9,6 +9,8 @@ struct rs_plan {
     int32_t M = 0, N = 0, C = 0, Ns = 0, L = 0, carrier = 1;
     double fc = 0, mu = 0, Fs = 0, Tb = 0, c0 = 0;
     double Kc = 0, Kb = 0, Kd = 0;  // binary64 phase constants
+    double Kf = 0, Krvp = 0;        // ... of the intra-chirp Doppler and video-phase variants
+    int32_t model = 0;              // rs_model_flags
     double *d_ant = nullptr;        // device tx[M][3] then rx[N][3]
     rs_form form = RS_FORM_MFMA_SPLIT16;
     rs_dtype dtype = RS_C64;

@@ -21,25 +21,49 @@ __device__ __forceinline__ double rs_distance(float x, float y, float z, const d
 // negative v).
 __device__ __forceinline__ double rs_frac(double v) { return v - __builtin_floor(v); }
 
-// Per-pixel quantities of one virtual channel (Sec. II, eq. (1)):
-//   R     = (|x - tx_m| + |x - rx_r|) / 2
-//   psi_f = frac(R * Kc)      carrier phase of sigma, cycles mod 1
-//   b     = R * Kb            beat frequency, cycles per fast-time sample
-//   beta  = v * Kd            Doppler phase per block, cycles
+// Phase arguments of a pixel in virtual channel c = m N + r (Sec. II,
+// eq. (1)): psi the carrier phase of sigma (cycles, not reduced), b the beat
+// frequency (cycles per fast-time sample), beta the Doppler phase per block
+// (cycles).  Without variant flags R = (|x - tx_m| + |x - rx_r|) / 2,
+// psi = R Kc, b = R Kb, beta = v Kd.  The flags (rs_model_flags) change psi
+// and b in the order below.
+__device__ __forceinline__ void rs_chan_args(const rs_job &J, float x, float y, float z, float v, int m,
+                                             const double *tx, const double *rx, double *psi, double *b,
+                                             double *beta)
+{
+    double Rc, Rb;
+    if (J.model & 1) {  // far field, eq. (2)
+        const double xd = (double)x, yd = (double)y, zd = (double)z;
+        const double Rp = __builtin_sqrt((xd * xd + yd * yd) + zd * zd);
+        const double ux = xd / Rp, uy = yd / Rp, uz = zd / Rp;
+        const double s = 0.5 * ((ux * (tx[0] + rx[0]) + uy * (tx[1] + rx[1])) + uz * (tx[2] + rx[2]));
+        Rc = Rp - s;
+        Rb = Rp;
+    } else {
+        Rc = 0.5 * (rs_distance(x, y, z, tx) + rs_distance(x, y, z, rx));
+        Rb = Rc;
+    }
+    *beta = (double)v * J.Kd;
+    *psi = Rc * J.Kc;
+    *b = Rb * J.Kb;
+    if (J.model & 8) *psi = *psi - (Rb * Rb) * J.Krvp;                    // residual video phase
+    if (J.model & 2) *psi = *psi - *beta * ((double)m / (double)J.M);     // Tx slot timing
+    if (J.model & 4) *b = *b - (double)v * J.Kf;                          // Doppler within the chirp
+}
+
+// Per-pixel quantities of one virtual channel: psi_f = frac(psi), b, beta, a.
 struct rs_pixel_args {
     double psi_f, b, beta;
     float a;
 };
 
-__device__ __forceinline__ rs_pixel_args rs_pixel(const rs_job &J, const double *tx,
+__device__ __forceinline__ rs_pixel_args rs_pixel(const rs_job &J, int m, const double *tx,
                                                   const double *rx, int64_t p)
 {
     rs_pixel_args o;
-    float x = J.x[p], y = J.y[p], z = J.z[p];
-    double R = 0.5 * (rs_distance(x, y, z, tx) + rs_distance(x, y, z, rx));
-    o.psi_f = rs_frac(R * J.Kc);
-    o.b = R * J.Kb;
-    o.beta = (double)J.vr[p] * J.Kd;
+    double psi;
+    rs_chan_args(J, J.x[p], J.y[p], J.z[p], J.vr[p], m, tx, rx, &psi, &o.b, &o.beta);
+    o.psi_f = rs_frac(psi);
     o.a = J.amp[p];
     return o;
 }

@@ -13,6 +13,7 @@ struct rs_job {
     void *partial;             // split-K partials [S][C][L][Ns] complex (f32 or f64)
     const double *ant;         // device antenna table: tx[M][3] then rx[N][3]
     double Kc, Kb, Kd;         // phase constants of the binary64 recipe
+    double Kf, Krvp;           // constants of the intra-chirp / video-phase variants
     int32_t M, N, Ns, L;
     int32_t n_tiles, l_tiles;  // output tiles along n and l
     int32_t S, chunk;          // pixel chunks and pixels per chunk
@@ -24,7 +25,7 @@ struct rs_job {
     int32_t *scale;            // [S] per-chunk strength exponent shift (matrix-core form)
     int32_t seg_begin, seg_end;  // 16-pixel steps of every chunk covered by this launch
     int32_t dtype;             // 0 = complex64, 1 = complex128
-    int32_t pad_;
+    int32_t model;             // signal-model variant flags (rs_model_flags)
 };
 
 // Job table of one launch.  With jobs == nullptr the single job `inline_job`

@@ -176,10 +176,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 const int64_t p = pb + (int64_t)blk * kPB + tid;
                 pix_par q;
                 if (p < pe) {
-                    const double R = 0.5 * (rs_distance(rxp, ryp, rzp, tx) + rs_distance(rxp, ryp, rzp, rx));
-                    q.psi_f = rs_frac(R * J.Kc);
-                    q.b = R * J.Kb;
-                    q.beta = (double)rvp * J.Kd;
+                    double psi;
+                    rs_chan_args(J, rxp, ryp, rzp, rvp, m, tx, rx, &psi, &q.b, &q.beta);
+                    q.psi_f = rs_frac(psi);
                     q.a = rap * a_scale;
                 } else {
                     q.psi_f = 0.0;

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
             if (tid < kKP) {
                 const int64_t p = p0 + tid;
                 if (p < pe) {
-                    rs_pixel_args a = rs_pixel(J, tx, rx, p);
+                    rs_pixel_args a = rs_pixel(J, m, tx, rx, p);
                     sPsi[tid] = a.psi_f;
                     sB[tid] = a.b;
                     sBeta[tid] = a.beta;

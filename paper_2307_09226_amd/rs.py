@@ -37,7 +37,7 @@ class rs_radar(ctypes.Structure):
                 ("Fs", ctypes.c_double), ("Tb", ctypes.c_double), ("c0", ctypes.c_double),
                 ("tx_xyz", ctypes.POINTER(ctypes.c_double)),
                 ("rx_xyz", ctypes.POINTER(ctypes.c_double)),
-                ("carrier_phase", ctypes.c_int32)]
+                ("carrier_phase", ctypes.c_int32), ("model", ctypes.c_int32)]
 
 
 class rs_pixels(ctypes.Structure):
@@ -230,7 +230,7 @@ def _radar_struct(radar):
                   float(radar.mu), float(radar.Fs), float(radar.Tb), float(radar.c0),
                   tx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                   rx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                  int(radar.carrier_phase))
+                  int(radar.carrier_phase), int(getattr(radar, "model", 0)))
     return st, (tx, rx)
 
 
