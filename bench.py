@@ -64,7 +64,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed steps first; the clock takes ~50 steps (~25 ms) of load to settle")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline single-frame measurement")
     ap.add_argument("--legs", default="plain,batch,doppler_time,serving,cpu",
