@@ -233,6 +233,42 @@ void rs_session_destroy(rs_session *s);
  * affected). */
 rs_status rs_session_inject_failure(rs_session *s, int32_t count);
 
+/* ------------------------------------------------- scenes on the device -- */
+/* The paper obtains each frame's pixels (range, strength, angle, velocity)
+ * from a rendered image (Sec. II, the paragraph after eq. (1)).  These calls
+ * ray-cast the synthetic stand-in scene on the device instead, so that a
+ * batch of frames never passes through host memory: an axis-aligned room
+ * [-W/2, W/2] x [0, D] x [-H/2, H/2] seen from the origin (boresight +y,
+ * array axis +x) and an optional ellipsoid pedestrian.
+ *   pixel p = j * g_az + i, azimuth -60 + 120 (i + 1/2) / g_az degrees,
+ *   elevation -30 + 60 (j + 1/2) / g_el degrees, unit ray
+ *   u = (cos el sin az, cos el cos az, sin el);
+ *   t = nearest positive hit on the walls x = +-W/2, y = D, z = +-H/2, or on
+ *   the ellipsoid |(x - c) / s| = 1 when that is nearer (it occludes);
+ *   position t u, strength |cos incidence| / t^2 * noise[p], radial velocity
+ *   -(v . u) on the pedestrian, 0 on the walls.
+ * Geometry in binary64, stored as float32 structure of arrays. */
+typedef struct {
+    double room_w, room_d, room_h;  /* metres */
+    int32_t pedestrian;             /* 1: the ellipsoid below is present */
+    int32_t reserved;               /* 0 */
+    double centre[3];               /* ellipsoid centre, metres */
+    double velocity[3];             /* m/s */
+    double semi_axes[3];            /* metres, > 0 */
+} rs_scene;
+
+/* Render `nframes` scenes over one g_az x g_el grid (P = g_az g_el pixels
+ * per frame).  scenes: HOST array [nframes] (copied in stream order).
+ * noise: device [nframes][P] strength factors (e.g. lognormal draws), or
+ * NULL for 1.  x, y, z, amp, vr: device [nframes][P] outputs, frame f at
+ * offset f P -- ready for rs_pixels / rs_beat_synthesize_batch.
+ * Errors: RS_E_INVALID (NULL scenes or outputs with nframes > 0,
+ * nframes < 0, g_az or g_el < 1, P * nframes > 2^31, non-positive or
+ * non-finite room or semi-axes), RS_E_NOMEM, RS_E_DEVICE. */
+rs_status rs_render_scenes(const rs_scene *scenes, int32_t nframes, int32_t g_az, int32_t g_el,
+                           const float *noise, float *x, float *y, float *z, float *amp, float *vr,
+                           void *hip_stream);
+
 /* -------------------------------------------------- range-Doppler maps -- */
 /* The processing the paper applies to each simulated cube (Sec. III): an FFT
  * over each coherent processing interval (one cube) gives the range-Doppler

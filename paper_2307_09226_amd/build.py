@@ -11,7 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librs.so")
-SOURCES = ["rs_api.hip", "rs_plain.hip", "rs_mfma.hip", "rs_reduce.hip", "rs_session.hip", "rs_rd.hip"]
+SOURCES = ["rs_api.hip", "rs_plain.hip", "rs_mfma.hip", "rs_reduce.hip", "rs_session.hip", "rs_rd.hip",
+           "rs_scene.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -65,6 +65,13 @@ class rs_session_stats(ctypes.Structure):
                 ("terms_done", ctypes.c_double)]
 
 
+class rs_scene(ctypes.Structure):
+    _fields_ = [("room_w", ctypes.c_double), ("room_d", ctypes.c_double), ("room_h", ctypes.c_double),
+                ("pedestrian", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("centre", ctypes.c_double * 3), ("velocity", ctypes.c_double * 3),
+                ("semi_axes", ctypes.c_double * 3)]
+
+
 class rs_rd_peak(ctypes.Structure):
     _fields_ = [("range_bin", ctypes.c_int32), ("doppler_bin", ctypes.c_int32),
                 ("power", ctypes.c_float), ("range_m", ctypes.c_float),
@@ -101,6 +108,8 @@ SIGNATURES = {
     "rs_session_destroy": (None, [_VP]),
     "rs_session_inject_failure": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "rs_range_doppler": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP]),
+    "rs_render_scenes": (ctypes.c_int, [ctypes.POINTER(rs_scene), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "rs_kernel_timer_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP)]),
     "rs_kernel_timer_attach": (ctypes.c_int, [_VP]),
     "rs_kernel_timer_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
@@ -291,6 +300,37 @@ def range_doppler(plan: Plan, cubes, skip_static: bool = True, stream=None):
     rs_range_doppler(plan, cubes, skip_static, power, dtime, peaks, stream)
     pk = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=RD_PEAK_DTYPE)
     return power, dtime, pk
+
+
+def scene_struct(room, ped=None) -> rs_scene:
+    """rs_scene of a room (W, D, H) and an optional pedestrian (centre,
+    velocity, semi_axes), e.g. the seeded input generator's Room and
+    Pedestrian."""
+    s = rs_scene()
+    s.room_w, s.room_d, s.room_h = float(room.W), float(room.D), float(room.H)
+    s.pedestrian = 0 if ped is None else 1
+    if ped is not None:
+        for k in range(3):
+            s.centre[k] = float(ped.centre[k])
+            s.velocity[k] = float(ped.velocity[k])
+            s.semi_axes[k] = float(ped.semi_axes[k])
+    return s
+
+
+def rs_render_scenes(scenes_: Sequence[rs_scene], g_az: int, g_el: int, noise=None, device="cuda:0",
+                     stream=None) -> List[DevicePixels]:
+    """Ray-cast len(scenes_) frames on the device; noise: device float32
+    [F * P] strength factors or None.  Returns one DevicePixels per frame
+    (views into five [F * P] tensors)."""
+    import torch
+    F = len(scenes_)
+    P = int(g_az) * int(g_el)
+    outs = [torch.empty(F * P, dtype=torch.float32, device=device) for _ in range(5)]
+    arr = (rs_scene * max(1, F))(*scenes_)
+    _check(lib.rs_render_scenes(arr, F, int(g_az), int(g_el),
+                                _ptr(noise) if noise is not None else None,
+                                *[_ptr(o) for o in outs], _stream_handle(stream)))
+    return [DevicePixels(*(o[f * P:(f + 1) * P] for o in outs)) for f in range(F)]
 
 
 def rs_beat_synthesize_batch(plan: Plan, frames: Sequence[DevicePixels], cubes, stream=None):

@@ -18,7 +18,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("rs_cube_plan", "rs_beat_synthesize", "rs_beat_synthesize_batch",
-                 "rs_session_create", "rs_session_submit", "rs_session_poll", "rs_range_doppler"):
+                 "rs_session_create", "rs_session_submit", "rs_session_poll", "rs_range_doppler",
+                 "rs_render_scenes"):
         assert must in names
 
 
@@ -67,6 +68,14 @@ def test_invalid_plan_arguments_rejected_on_host():
     assert rs.lib.rs_beat_synthesize(None, None, None, None) == rs.RS_E_INVALID
     assert rs.lib.rs_session_submit(None, None, None, None, None) == rs.RS_E_INVALID
     assert rs.lib.rs_range_doppler(None, None, 1, 1, None, None, None, None) == rs.RS_E_INVALID
+    assert rs.lib.rs_render_scenes(None, 1, 8, 8, None, None, None, None, None, None, None) == rs.RS_E_INVALID
+    sc = (rs.rs_scene * 1)()
+    sc[0].room_w, sc[0].room_d, sc[0].room_h = 4.0, -1.0, 3.0
+    fake = ctypes.c_void_p(256)   # never dereferenced: validation fails first
+    assert rs.lib.rs_render_scenes(sc, 1, 8, 8, None, fake, fake, fake, fake, fake, None) == rs.RS_E_INVALID
+    assert rs.lib.rs_render_scenes(sc, -1, 8, 8, None, fake, fake, fake, fake, fake, None) == rs.RS_E_INVALID
+    sc[0].room_d = 5.0
+    assert rs.lib.rs_render_scenes(sc, 1, 0, 8, None, fake, fake, fake, fake, fake, None) == rs.RS_E_INVALID
     out = ctypes.c_size_t()
     assert rs.lib.rs_plan_workspace_bytes(None, 0, ctypes.byref(out)) == rs.RS_E_INVALID
     rs.lib.rs_plan_destroy(None)
