@@ -292,6 +292,33 @@ def doppler_time_leg(rs, scenes, dev, timer):
     # algorithmic bytes: every cube entry read once (complex64), the power
     # map written once (float32)
     rd_bytes = F * radar.C * radar.L * radar.Ns * 8 + F * radar.Ns * radar.L * 4
+
+    # the same walk with the frames ray-cast on the device (strength factors
+    # drawn on the device): no pixel passes through host memory
+    g = 256
+    room = scenes.Room(W=12.0, D=10.0)
+    structs = rs.scene_array([rs.scene_struct(room, scenes.Pedestrian(centre=c, velocity=v))
+                              for c, v in zip(cw.centres, cw.velocities)])
+    pix = [torch.empty(F * g * g, dtype=torch.float32, device=dev) for _ in range(5)]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    noise = torch.empty(F * g * g, dtype=torch.float32, device=dev).log_normal_(0.0, 0.5, generator=gen)
+    holder = {}
+
+    def render():
+        holder["frames"] = rs.rs_render_scenes(structs, g, g, noise, dev, out=pix)
+    rnd_wall, _ = timed_steps(render, 10, 2)
+    render_ms = rnd_wall * 1e3 / 10
+
+    def pipeline():
+        fr = rs.rs_render_scenes(structs, g, g, noise, dev, out=pix)
+        rs.rs_beat_synthesize_batch(plan, fr, cubes)
+        rs.rs_range_doppler(plan, cubes, True, power, dtime, peaks)
+    pwall, _ = timed_steps(pipeline, 3, 1)
+    torch.cuda.synchronize()
+    pk2 = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=rs.RD_PEAK_DTYPE)
+    err2 = np.abs(pk2["velocity_mps"].astype(np.float64) - cw.v_radial)
+    render_bytes = F * g * g * (20 + 4)
     plan.close()
     return {"workload": f"walking circle, radius 3 m, {F} frames at 24 Hz (4.52 m/s), room 12 x 10 m, "
                         "256x256 px, 3 Tx x 4 Rx, Ns=256, L=128",
@@ -306,6 +333,13 @@ def doppler_time_leg(rs, scenes, dev, timer):
             "doppler_bin_mps": float(radar.c0 / (2 * radar.fc * radar.Tb * radar.L)),
             "corr_v_est_v_true": float(np.corrcoef(v_est, cw.v_radial)[0, 1]),
             "paper_E_velo_mps": 1.3,
+            "device_rendered": {
+                "render_ms": render_ms,
+                "render_roofline": {"bound": "hbm", "achieved": render_bytes / (render_ms * 1e-3) / 1e9,
+                                    "peak": 8000.0, "unit": "GB/s",
+                                    "frac": render_bytes / (render_ms * 1e-3) / 8e12},
+                "render_synth_rd_ms": pwall * 1e3 / 3,
+                "E_velo_mps": float(np.mean(err2)), "max_abs_error_mps": float(err2.max())},
             "v_est": [round(float(v), 3) for v in v_est],
             "v_true": [round(float(v), 3) for v in cw.v_radial]}
 

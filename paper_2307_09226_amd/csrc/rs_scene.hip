@@ -20,13 +20,12 @@ __global__ __launch_bounds__(256) void k_render(const rs_scene *scenes, int64_t 
     const int64_t f = g / P, p = g % P;
     const rs_scene &S = scenes[f];
     const int i = (int)(p % g_az), j = (int)(p / g_az);
-    // ray direction of the pixel centre
-    const double deg = 3.14159265358979323846 / 180.0;
-    const double az = (-60.0 + 120.0 * ((double)i + 0.5) / (double)g_az) * deg;
-    const double el = (-30.0 + 60.0 * ((double)j + 0.5) / (double)g_el) * deg;
+    // ray direction of the pixel centre (angles in degrees / 180 = half turns)
+    const double az = (-60.0 + 120.0 * ((double)i + 0.5) / (double)g_az) / 180.0;
+    const double el = (-30.0 + 60.0 * ((double)j + 0.5) / (double)g_el) / 180.0;
     double saz, caz, sel, cel;
-    sincos(az, &saz, &caz);
-    sincos(el, &sel, &cel);
+    sincospi(az, &saz, &caz);
+    sincospi(el, &sel, &cel);
     const double u[3] = {cel * saz, cel * caz, sel};
     // nearest wall: planes x = +-W/2, y = D, z = +-H/2
     const double inf = __builtin_huge_val();

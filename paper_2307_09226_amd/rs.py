@@ -317,16 +317,23 @@ def scene_struct(room, ped=None) -> rs_scene:
     return s
 
 
-def rs_render_scenes(scenes_: Sequence[rs_scene], g_az: int, g_el: int, noise=None, device="cuda:0",
-                     stream=None) -> List[DevicePixels]:
-    """Ray-cast len(scenes_) frames on the device; noise: device float32
-    [F * P] strength factors or None.  Returns one DevicePixels per frame
-    (views into five [F * P] tensors)."""
+def scene_array(scenes_: Sequence[rs_scene]):
+    """ctypes array of rs_scene records (build once, render many times)."""
+    return (rs_scene * max(1, len(scenes_)))(*scenes_)
+
+
+def rs_render_scenes(scenes_, g_az: int, g_el: int, noise=None, device="cuda:0",
+                     stream=None, out=None) -> List[DevicePixels]:
+    """Ray-cast len(scenes_) frames on the device.  scenes_: rs_scene records
+    or a scene_array(); noise: device float32 [F * P] strength factors or
+    None; out: five float32 [F * P] device tensors to fill, or None for new
+    ones.  Returns one DevicePixels per frame (views into the five tensors)."""
     import torch
     F = len(scenes_)
     P = int(g_az) * int(g_el)
-    outs = [torch.empty(F * P, dtype=torch.float32, device=device) for _ in range(5)]
-    arr = (rs_scene * max(1, F))(*scenes_)
+    outs = out if out is not None else [torch.empty(F * P, dtype=torch.float32, device=device)
+                                        for _ in range(5)]
+    arr = scenes_ if isinstance(scenes_, ctypes.Array) else scene_array(scenes_)
     _check(lib.rs_render_scenes(arr, F, int(g_az), int(g_el),
                                 _ptr(noise) if noise is not None else None,
                                 *[_ptr(o) for o in outs], _stream_handle(stream)))
