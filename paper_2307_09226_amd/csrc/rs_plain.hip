@@ -3,15 +3,19 @@
 // Y[c][l][n] = sum_p a_p exp(j2pi(psi_{p,c} + b_{p,c} n - beta_p l))  (Sec. II,
 // eq. (1) per virtual channel, pixel sum of eq. (2)).  Each term is the
 // product F[p][n] * D[p][l] with
-//   F[p][n] = exp(j2pi wrap(psi_f + frac(b n)))      (binary64 sincospi)
-//   D[p][l] = a_p exp(-j2pi frac(beta l))             (binary64 sincospi)
-// and is accumulated with four binary64 FMAs (8 flop per term).
+//   F[p][n] = exp(j2pi wrap(psi_f + frac(b n)))
+//   D[p][l] = a_p exp(-j2pi frac(beta l))
+// in binary64, accumulated with four binary64 FMAs (8 flop per term).
 //
 // Work item = (channel, 64-row n tile, TL-column l tile, pixel chunk).  Per
 // step of 16 pixels the workgroup evaluates the 16 x 64 F and 16 x TL D
 // phasors once into LDS; each thread then owns a 4 (n) x TL/16 (l) block of
-// binary64 accumulators.  Chunks write binary64 partial tiles that the
-// reduce kernel sums in a fixed order.
+// binary64 accumulators.  A thread evaluates a run of consecutive phasors of
+// one pixel: the first directly (binary64 sincospi of the reduced phase),
+// the others by binary64 rotation with exp(j2pi frac(b)) or
+// exp(-j2pi frac(beta)), at most 7 rotations (~1e-15 relative).  Chunks
+// write binary64 partial tiles that the reduce kernel sums in a fixed
+// order.
 #include "rs_device.h"
 
 namespace {
@@ -68,24 +72,41 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
                 }
             }
             __syncthreads();
-            // fast-time phasors: F = exp(j 2pi phi), phi = wrap(psi_f + frac(b n))
-            for (int e = tid; e < kKP * kTN; e += 256) {
-                const int q = e / kTN, nn = e % kTN;
-                const double th = sB[q] * (double)(n0 + nn);
-                double phi = sPsi[q] + rs_frac(th);
+            {
+                // thread = (pixel q, run r of consecutive rows / columns)
+                const int q = tid >> 4, r = tid & 15;
+                // fast-time phasors F = exp(j 2pi phi), phi = wrap(psi_f + frac(b n)),
+                // rows n0 + 4r .. n0 + 4r + 3
+                constexpr int FR = kTN / 16;
+                const double b = sB[q];
+                double phi = sPsi[q] + rs_frac(b * (double)(n0 + FR * r));
                 phi = phi - __builtin_floor(phi + 0.5);
-                double sv, cv;
-                sincospi(2.0 * phi, &sv, &cv);
-                sF[q][nn] = make_double2(cv, sv);
-            }
-            // slow-time phasors: D = a exp(-j 2pi frac(beta l))
-            for (int e = tid; e < kKP * TL; e += 256) {
-                const int q = e / TL, ll = e % TL;
-                const double ph = rs_frac(sBeta[q] * (double)(l0 + ll));
-                double sv, cv;
-                sincospi(2.0 * ph, &sv, &cv);
-                const double a = sA[q];
-                sD[q][ll] = make_double2(a * cv, -(a * sv));
+                double fs, fc, rs_, rc;
+                sincospi(2.0 * phi, &fs, &fc);
+                sincospi(2.0 * rs_frac(b), &rs_, &rc);
+#pragma unroll
+                for (int k = 0; k < FR; ++k) {
+                    sF[q][FR * r + k] = make_double2(fc, fs);
+                    const double cn = __builtin_fma(fc, rc, -(fs * rs_));
+                    fs = __builtin_fma(fc, rs_, fs * rc);
+                    fc = cn;
+                }
+                // slow-time phasors D = a exp(-j 2pi frac(beta l)), columns
+                // l0 + DR r .. l0 + DR r + DR - 1
+                constexpr int DR = TL / 16;
+                const double beta = sBeta[q], a = sA[q];
+                double ds, dc, ts, tc;
+                sincospi(2.0 * rs_frac(beta * (double)(l0 + DR * r)), &ds, &dc);
+                sincospi(2.0 * rs_frac(beta), &ts, &tc);
+                dc *= a;
+                ds *= a;
+#pragma unroll
+                for (int k = 0; k < DR; ++k) {
+                    sD[q][DR * r + k] = make_double2(dc, -ds);
+                    const double cn = __builtin_fma(dc, tc, -(ds * ts));
+                    ds = __builtin_fma(dc, ts, ds * tc);
+                    dc = cn;
+                }
             }
             __syncthreads();
 #pragma unroll 4
