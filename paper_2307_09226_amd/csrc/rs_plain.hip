@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
                 }
             }
             __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
             for (int q = 0; q < kKP; ++q) {
                 double2 f[4], d[NJ];
 #pragma unroll
