@@ -92,3 +92,33 @@ def test_repeatable_bitwise():
     a = synth(radar, px, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64)
     b = synth(radar, px, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, ws=True)
     assert np.array_equal(a, b)
+
+
+def test_largest_serving_request_sampled():
+    """The largest request shape of the serving mix (12 x 16 array, Ns 512,
+    L 256, a 512 x 512-pixel frame): 192 channels, 6.6e12 terms, a 201 MB
+    cube, alone and through a session, on sampled entries."""
+    import torch
+    rs = _rs()
+    radar = scenes.radar_for(12, 16, 512, 256, Fs=512 / 25.6e-6, Tb=12 * 40e-6)
+    px = scenes.scene_small(seed=9, grid=512, pedestrian=True)
+    assert px.P == 512 * 512
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
+    dpx = rs.DevicePixels.from_host(px)
+    cube = rs.new_cube(plan)
+    rs.rs_beat_synthesize(plan, dpx, cube)
+    torch.cuda.synchronize()
+    c, l, n = sample_indices(radar.cube_shape(), 160, seed=9)
+    got = cube[torch.as_tensor(c, device="cuda:0").long(), torch.as_tensor(l, device="cuda:0").long(),
+               torch.as_tensor(n, device="cuda:0").long()].cpu().numpy()
+    ref = oracle.entries(radar, px, c, l, n)
+    rel, mx = errors(got, ref)
+    print(f"largest request relL2={rel:.3e} maxabs={mx:.3e}")
+    assert rel <= GATE_MFMA and mx <= GATE_MFMA
+    sess = rs.Session(hbm_budget=2 << 30, max_slots=2)
+    cube2 = rs.new_cube(plan)
+    t = sess.submit(plan, dpx, cube2)
+    sess.drain()
+    assert sess.poll(t)[0] == rs.RS_REQ_DONE
+    assert torch.equal(cube, cube2)
+    sess.close()
