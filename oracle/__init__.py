@@ -94,20 +94,23 @@ class Oracle:
         return s, (tx, rx)
 
     @staticmethod
-    def _pixels(px):
+    def _pixels(px, radar):
+        """Strengths are [P], or [L][P] (block l's strengths in row l) when the
+        radar's model has the block-strength flag (16)."""
         arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in
                 (px.x, px.y, px.z, px.amp, px.vr)]
         P = int(arrs[0].shape[0])
-        for a in arrs:
-            if a.shape != (P,):
-                raise ValueError("pixel arrays must be 1-D and of equal length")
+        for i, a in enumerate(arrs):
+            want = (int(radar.L), P) if i == 3 and int(getattr(radar, "model", 0)) & 16 else (P,)
+            if a.shape != want:
+                raise ValueError(f"pixel array {i} has shape {a.shape}, expected {want}")
         return _Pixels(P, *[_f32p(a) for a in arrs]), arrs
 
     # -- computations -----------------------------------------------------------
     def cube(self, radar, px, threads: int = 0) -> np.ndarray:
         """Full cube Y[C][L][Ns] (complex128) by the direct sum."""
         rs, keep_r = self._radar(radar)
-        ps, keep_p = self._pixels(px)
+        ps, keep_p = self._pixels(px, radar)
         out = np.empty((radar.M * radar.N, radar.L, radar.Ns, 2), dtype=np.float64)
         if self.lib.orc_cube(ctypes.byref(rs), ctypes.byref(ps), _f64p(out), threads):
             raise ValueError("oracle rejected the arguments")
@@ -120,7 +123,7 @@ class Oracle:
         n = np.ascontiguousarray(n, dtype=np.int32)
         K = int(c.shape[0])
         rs, keep_r = self._radar(radar)
-        ps, keep_p = self._pixels(px)
+        ps, keep_p = self._pixels(px, radar)
         out = np.empty((K, 2), dtype=np.float64)
         ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         if self.lib.orc_entries(ctypes.byref(rs), ctypes.byref(ps), K, ip(c), ip(l), ip(n),
@@ -131,7 +134,7 @@ class Oracle:
     def marginal_n(self, radar, px, threads: int = 0) -> np.ndarray:
         """Closed-form sum over fast time, S[C][L] = sum_n Y[c][l][n]."""
         rs, keep_r = self._radar(radar)
-        ps, keep_p = self._pixels(px)
+        ps, keep_p = self._pixels(px, radar)
         out = np.empty((radar.M * radar.N, radar.L, 2), dtype=np.float64)
         if self.lib.orc_marginal_n(ctypes.byref(rs), ctypes.byref(ps), _f64p(out), threads):
             raise ValueError("oracle rejected the arguments")
@@ -140,7 +143,7 @@ class Oracle:
     def marginal_l(self, radar, px, threads: int = 0) -> np.ndarray:
         """Closed-form sum over slow time, S[C][Ns] = sum_l Y[c][l][n]."""
         rs, keep_r = self._radar(radar)
-        ps, keep_p = self._pixels(px)
+        ps, keep_p = self._pixels(px, radar)
         out = np.empty((radar.M * radar.N, radar.Ns, 2), dtype=np.float64)
         if self.lib.orc_marginal_l(ctypes.byref(rs), ctypes.byref(ps), _f64p(out), threads):
             raise ValueError("oracle rejected the arguments")

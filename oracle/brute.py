@@ -22,6 +22,13 @@ import mpmath as mp
 DPS = 50
 
 
+def _amp(px, p, l):
+    """Strength of pixel p in block l: amp is [P], or [L][P] when the
+    strength varies over the TDM blocks."""
+    a = px.amp
+    return float(a[l, p]) if a.ndim == 2 else float(a[p])
+
+
 def _recipe_args(radar, px):
     f64 = np.float64
     Kc = (f64(2.0) * f64(radar.fc)) / f64(radar.c0) if radar.carrier_phase else f64(0.0)
@@ -63,7 +70,7 @@ def cube_recipe(radar, px, dps: int = DPS) -> np.ndarray:
                         ph = (np.float64(px.vr[p]) * Kd) * np.float64(l)
                         ph_f = ph - np.floor(ph)
                         phi = mp.mpf(float(psi_f)) + mp.mpf(float(th_f)) - mp.mpf(float(ph_f))
-                        s += mp.mpf(float(px.amp[p])) * mp.expj(2 * mp.pi * phi)
+                        s += mp.mpf(_amp(px, p, l)) * mp.expj(2 * mp.pi * phi)
                     out[c, l, n] = complex(s)
     return out
 
@@ -101,7 +108,7 @@ def cube_exact(radar, px, dps: int = DPS) -> np.ndarray:
                         beat = 2 * mu * Rp / c0 * n / Fs
                         fD = 2 * mp.mpf(float(px.vr[p])) * fc / c0
                         phi = sigma_phase + beat - fD * l * Tb
-                        s += mp.mpf(float(px.amp[p])) * mp.expj(2 * mp.pi * phi)
+                        s += mp.mpf(_amp(px, p, l)) * mp.expj(2 * mp.pi * phi)
                     out[c, l, n] = complex(s)
     return out
 
@@ -123,7 +130,9 @@ def phase_error_bound(radar, px) -> np.ndarray:
     n = np.arange(radar.Ns, dtype=np.float64)
     l = np.arange(radar.L, dtype=np.float64)
     beta = np.abs(px.vr.astype(np.float64) * Kd)
-    a = px.amp.astype(np.float64)
+    a = np.abs(px.amp.astype(np.float64))
+    if a.ndim == 2:  # strengths per block: bound with the largest
+        a = a.max(axis=0)
     C = radar.M * radar.N
     out = np.zeros((C, radar.L, radar.Ns))
     for c in range(C):

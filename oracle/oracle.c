@@ -46,6 +46,11 @@
  *   INTRA_CHIRP (4) Doppler shift within the chirp, with the sign of the
  *                   slow-time term (the echo delay shrinks as an approaching
  *                   scatterer closes in): b -= v Kf, Kf = (2 fc)/(c0 Fs)
+ * One variant changes the strength instead of the phase arguments:
+ *   BLOCK_STRENGTH (16)  eq. (1)'s sigma depends on the TDM block l: the
+ *                   strength of pixel p in block l is amp[l*P + p] (amp holds
+ *                   L rows of P values), the same for every channel, so
+ *                   a_p becomes a_{p,l} in the sum above.
  *
  * Output layout: interleaved (re, im) doubles, [C][L][Ns] row-major, n fastest.
  */
@@ -65,7 +70,8 @@ typedef struct {
     int32_t model;    /* signal-model variant flags, see above */
 } orc_radar;
 
-enum { ORC_FAR_FIELD = 1, ORC_TDM_SLOT = 2, ORC_INTRA_CHIRP = 4, ORC_RVP = 8, ORC_MODEL_ALL = 15 };
+enum { ORC_FAR_FIELD = 1, ORC_TDM_SLOT = 2, ORC_INTRA_CHIRP = 4, ORC_RVP = 8, ORC_BLOCK_STRENGTH = 16,
+       ORC_MODEL_ALL = 31 };
 
 typedef struct {
     int64_t P;
@@ -142,6 +148,13 @@ static void chan_args(const orc_radar *r, const orc_consts *k, const orc_pixels 
 
 static double frac(double v) { return v - floor(v); }
 
+/* Strength of pixel p in TDM block l: a_p, or a_{p,l} with BLOCK_STRENGTH. */
+static double strength(const orc_radar *r, const orc_pixels *px, int64_t p, int l)
+{
+    if (r->model & ORC_BLOCK_STRENGTH) return (double)px->amp[(int64_t)l * px->P + p];
+    return (double)px->amp[p];
+}
+
 /* One term a * exp(j 2 pi (psi + b n - beta l)) by the fixed recipe. */
 static void term(double psi, double b, double beta, double a, int n, int l, double *re, double *im)
 {
@@ -184,7 +197,7 @@ int orc_cube(const orc_radar *r, const orc_pixels *px, double *out, int nthreads
         for (int64_t p = 0; p < P; ++p) {
             double psi, b, beta;
             chan_args(r, &k, px, p, c, &psi, &b, &beta);
-            double a = (double)px->amp[p];
+            double a = strength(r, px, p, l);
             for (int n = 0; n < Ns; ++n) {
                 double re, im;
                 term(psi, b, beta, a, n, l, &re, &im);
@@ -216,7 +229,7 @@ int orc_entries(const orc_radar *r, const orc_pixels *px, int64_t K,
             double psi, b, beta;
             chan_args(r, &kk, px, p, cs[k], &psi, &b, &beta);
             double re, im;
-            term(psi, b, beta, (double)px->amp[p], ns[k], ls[k], &re, &im);
+            term(psi, b, beta, strength(r, px, p, ls[k]), ns[k], ls[k], &re, &im);
             sre += re;
             sim += im;
         }
@@ -268,7 +281,7 @@ int orc_marginal_n(const orc_radar *r, const orc_pixels *px, double *out, int nt
             double gr, gi;
             geom(r->Ns, b, &gr, &gi);
             double cr = cos(TWO_PI * ph), ci = sin(TWO_PI * ph);
-            double a = (double)px->amp[p];
+            double a = strength(r, px, p, l);
             sre += a * (cr * gr - ci * gi);
             sim += a * (cr * gi + ci * gr);
         }
@@ -279,7 +292,9 @@ int orc_marginal_n(const orc_radar *r, const orc_pixels *px, double *out, int nt
 }
 
 /* Slow-time marginal S[c][n] = sum_l Y[c][l][n] in closed form:
- * sum_p a_p exp(j 2 pi (psi + b n)) G_L(-beta). */
+ * sum_p a_p exp(j 2 pi (psi + b n)) G_L(-beta).  With BLOCK_STRENGTH the
+ * slow-time factor sum_l a_{p,l} exp(-j 2 pi beta l) has no closed form and
+ * is summed over l per pixel, still apart from the fast-time phasor. */
 int orc_marginal_l(const orc_radar *r, const orc_pixels *px, double *out, int nthreads)
 {
     if (!valid(r, px) || !out) return 1;
@@ -295,10 +310,18 @@ int orc_marginal_l(const orc_radar *r, const orc_pixels *px, double *out, int nt
             double psi, b, beta;
             chan_args(r, &k, px, p, c, &psi, &b, &beta);
             double ph = frac(psi) + frac(b * (double)n);
-            double gr, gi;
-            geom(r->L, -beta, &gr, &gi);
+            double gr = 0.0, gi = 0.0, a = 1.0;
+            if (r->model & ORC_BLOCK_STRENGTH) {
+                for (int l = 0; l < r->L; ++l) {
+                    double al = strength(r, px, p, l), th = TWO_PI * frac(beta * (double)l);
+                    gr += al * cos(th);
+                    gi -= al * sin(th);
+                }
+            } else {
+                geom(r->L, -beta, &gr, &gi);
+                a = (double)px->amp[p];
+            }
             double cr = cos(TWO_PI * ph), ci = sin(TWO_PI * ph);
-            double a = (double)px->amp[p];
             sre += a * (cr * gr - ci * gi);
             sim += a * (cr * gi + ci * gr);
         }

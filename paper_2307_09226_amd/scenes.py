@@ -129,7 +129,8 @@ class Pixels:
         return int(self.x.shape[0])
 
     def take(self, idx) -> "Pixels":
-        return Pixels(self.x[idx], self.y[idx], self.z[idx], self.amp[idx], self.vr[idx],
+        amp = self.amp[:, idx] if self.amp.ndim == 2 else self.amp[idx]
+        return Pixels(self.x[idx], self.y[idx], self.z[idx], amp, self.vr[idx],
                       None if self.cos_inc is None else self.cos_inc[idx],
                       None if self.is_ped is None else self.is_ped[idx])
 
@@ -421,6 +422,20 @@ def tiny_scene(seed: int, P: int, span: float = 6.0, vmax: float = 3.0) -> Pixel
     vr = rng.uniform(-vmax, vmax, P)
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return Pixels(f32(x), f32(y), f32(z), f32(amp), f32(vr))
+
+
+def block_strengths(px: Pixels, L: int, seed: int, depth: float = 0.5) -> Pixels:
+    """The same scatterers with a strength per TDM block (float32 [L][P],
+    row l = block l): each pixel's strength swings slowly over the CPI,
+    a_p (1 + depth sin(2pi (f_p l / L) + phase_p)) with f_p ~ U[0, 3) cycles
+    per CPI and phase_p ~ U[0, 2pi), as an aspect-dependent return would."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.0, 3.0, px.P)
+    ph = rng.uniform(0.0, 2 * np.pi, px.P)
+    l = np.arange(L, dtype=np.float64)[:, None]
+    a = px.amp.astype(np.float64)[None, :] * (1.0 + depth * np.sin(2 * np.pi * f[None, :] * l / L + ph[None, :]))
+    return Pixels(px.x, px.y, px.z, np.ascontiguousarray(a, dtype=np.float32), px.vr,
+                  px.cos_inc, px.is_ped)
 
 
 # ----------------------------------------------------------------------------

@@ -367,7 +367,83 @@ def pin_far_field_model(o):
     assert errs[1] < errs[0] / 30, errs
 
 
-ALL_PINS = [pin_model_zero_is_default, pin_slot_timing_alias, pin_dechirp_physics,
+# ----------------------------------------------------------------------------
+# Strength per TDM block (flag 16): eq. (1)'s sigma_{m,n,l} varying with l
+def _block_amp(px, rows):
+    """Pixels whose [L][P] strengths are `rows` (float32)."""
+    return scenes.Pixels(px.x, px.y, px.z, np.ascontiguousarray(rows, dtype=np.float32), px.vr)
+
+
+def pin_block_strength_reductions(o):
+    """Equal rows reproduce the constant-strength cube bitwise; power-of-two
+    row factors g_l scale block l of the cube by exactly g_l (every term of
+    block l is scaled by g_l, a power of two)."""
+    rng = np.random.default_rng(61)
+    r = scenes.radar_for(2, 3, 8, 6, Fs=5e6, Tb=80e-6)
+    r.tx, r.rx = _random_antennas(rng, 2, 3, r.wavelength)
+    px = scenes.tiny_scene(62, 13)
+    base = o.cube(r, px)
+    rb = _with_model(r, 16)
+    same = _block_amp(px, np.tile(px.amp, (r.L, 1)))
+    assert np.array_equal(o.cube(rb, same), base)
+    g = 2.0 ** rng.integers(-3, 4, r.L)
+    scaled = _block_amp(px, g[:, None] * px.amp[None, :])
+    assert np.array_equal(o.cube(rb, scaled), g[None, :, None] * base)
+
+
+def pin_block_strength_sidebands(o):
+    """One scatterer whose strength follows 1 + cos(2pi k0 l / L) over the
+    blocks: its slow-time spectrum is the carrier line G_L(d/L - beta) plus
+    two half-height sidebands G_L((d -+ k0)/L - beta) / 2, where
+    G_L(x) = sum_l exp(j2pi x l), here evaluated in 40-digit arithmetic with
+    beta from the float32 velocity."""
+    r = _with_model(_colocated_radar(Ns=16, L=32), 16)
+    px = _one_pixel(0.3, 4.1, -0.2, 1.0, 2.3)
+    k0 = 5
+    l = np.arange(r.L)
+    px = _block_amp(px, (1.0 + np.cos(2 * np.pi * k0 * l / r.L))[:, None])
+    Y = o.cube(r, px)
+    spec = np.fft.ifft(Y[0, :, 0]) * r.L   # sum_l Y[l] exp(+j2pi d l / L)
+    with mp.workdps(40):
+        beta = 2 * mp.mpf(r.fc) * mp.mpf(r.Tb) * mp.mpf(float(px.vr[0])) / mp.mpf(r.c0)
+        G = lambda x: mp.fsum(mp.expj(2 * mp.pi * x * j) for j in range(r.L))
+        want = [G(mp.mpf(d) / r.L - beta) + (G(mp.mpf(d - k0) / r.L - beta) + G(mp.mpf(d + k0) / r.L - beta)) / 2
+                for d in range(r.L)]
+    want = np.array([complex(w) for w in want])
+    # the float32 row values (1 + cos) carry ~6e-8 relative rounding
+    assert np.max(np.abs(np.abs(spec) - np.abs(want))) < 1e-6 * r.L
+    top = sorted(np.argsort(np.abs(spec))[-3:])
+    j0 = int(round(float(beta) * r.L)) % r.L
+    assert top == sorted({j0, (j0 + k0) % r.L, (j0 - k0) % r.L}), (top, j0)
+
+
+def pin_block_strength_brute(o):
+    """Tiny scene with random strengths per block against the exact (50-digit)
+    sum: every entry within the binary64 phase-error bound; the entries and
+    both marginals (the slow-time one summed per pixel over l) agree with
+    the cube."""
+    rng = np.random.default_rng(71)
+    r = _with_model(scenes.radar_for(2, 2, 4, 3, Fs=5e6, Tb=80e-6), 16)
+    r.tx, r.rx = _random_antennas(rng, 2, 2, r.wavelength)
+    base = scenes.tiny_scene(72, 4)
+    px = _block_amp(base, rng.lognormal(0.0, 0.7, (r.L, base.P)))
+    ref = brute.cube_exact(r, px)
+    bound = brute.phase_error_bound(r, px)
+    Y = o.cube(r, px)
+    assert np.all(np.abs(Y - ref) <= bound), float(np.max(np.abs(Y - ref) / bound))
+    c = rng.integers(0, r.C, 20)
+    ll = rng.integers(0, r.L, 20)
+    n = rng.integers(0, r.Ns, 20)
+    assert np.array_equal(o.entries(r, px, c, ll, n), Y[c, ll, n])
+    r2 = _with_model(scenes.radar_for(2, 3, 16, 8, Fs=5e6, Tb=80e-6), 16)
+    px2 = scenes.block_strengths(scenes.tiny_scene(73, 29), r2.L, seed=74)
+    Y2 = o.cube(r2, px2)
+    assert relerr(Y2.sum(axis=2), o.marginal_n(r2, px2)) < 1e-11
+    assert relerr(Y2.sum(axis=1), o.marginal_l(r2, px2)) < 1e-11
+
+
+ALL_PINS = [pin_block_strength_reductions, pin_block_strength_sidebands, pin_block_strength_brute,
+            pin_model_zero_is_default, pin_slot_timing_alias, pin_dechirp_physics,
             pin_far_field_model, pin_empty_scene, pin_single_scatterer_closed_form, pin_range_and_doppler_peaks,
             pin_marginals, pin_linearity, pin_static_scene_slices, pin_doppler_alias,
             pin_eq1_per_rx, pin_far_field, pin_entries_match_cube, pin_brute_recipe,

@@ -30,8 +30,8 @@ MUTANTS = [
     ("dz_uses_y", "double dz = (double)z - ant[2];", "double dz = (double)z - ant[1];"),
     ("dropped_dz", "return sqrt((dx * dx + dy * dy) + dz * dz);", "return sqrt(dx * dx + dy * dy);"),
     ("first_pixel_skipped", "for (int64_t p = 0; p < P; ++p) {", "for (int64_t p = 1; p < P; ++p) {"),
-    ("entries_n_l_swapped", "(double)px->amp[p], ns[k], ls[k], &re, &im);",
-     "(double)px->amp[p], ls[k] % r->Ns, ns[k] % r->L, &re, &im);"),
+    ("entries_n_l_swapped", "strength(r, px, p, ls[k]), ns[k], ls[k], &re, &im);",
+     "strength(r, px, p, ls[k]), ls[k] % r->Ns, ns[k] % r->L, &re, &im);"),
     ("marginal_l_sign", "geom(r->L, -beta, &gr, &gi);", "geom(r->L, beta, &gr, &gi);"),
     ("marginal_n_length", "geom(r->Ns, b, &gr, &gi);", "geom(r->Ns - 1, b, &gr, &gi);"),
     ("geom_phase_half", "double ang = PI * fmod((double)(N - 1) * xr, 2.0);",
@@ -49,6 +49,13 @@ MUTANTS = [
     ("ff_beat_uses_carrier_range", "Rb = Rp;", "Rb = Rc;"),
     ("ff_no_half", "double s = 0.5 * ((ux", "double s = ((ux"),
     ("ff_sign", "Rc = Rp - s;", "Rc = Rp + s;"),
+    ("block_strength_ignored", "if (r->model & ORC_BLOCK_STRENGTH) return", "if (0) return"),
+    ("block_strength_transposed", "px->amp[(int64_t)l * px->P + p]", "px->amp[(int64_t)p * r->L + l]"),
+    ("block_strength_next_block", "px->amp[(int64_t)l * px->P + p]",
+     "px->amp[(int64_t)((l + 1) % r->L) * px->P + p]"),
+    ("entries_block_of_row_zero", "term(psi, b, beta, strength(r, px, p, ls[k]),",
+     "term(psi, b, beta, strength(r, px, p, 0),"),
+    ("marginal_l_block_sign", "gi -= al * sin(th);", "gi += al * sin(th);"),
     ("ff_ignores_rx", "uz * (tx[2] + rx[2]));", "uz * (tx[2] + rx[2])) + 0.5 * ((ux * (tx[0] - rx[0]) + uy * (tx[1] - rx[1])) + uz * (tx[2] - rx[2]));"),
 ]
 
