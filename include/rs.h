@@ -20,8 +20,9 @@
  * a_p is the pixel strength (eq. (2)'s P_r, applied as an amplitude) and v_p
  * its radial velocity (eq. (2)'s V), positive when approaching.  T_b is the
  * TDM block period (one block holds M chirps).  The intra-block Tx slot
- * offset, residual video phase and intra-chirp Doppler are not in eq. (1)
- * and are not modelled.
+ * offset, residual video phase, intra-chirp Doppler and a strength that
+ * changes from block to block are not in this form of eq. (1); each is
+ * available as a variant (rs_model_flags).
  *
  * Two forms compute Y:
  *   RS_FORM_FP64_DIRECT   binary64 phasors and binary64 complex
@@ -90,12 +91,19 @@ typedef enum { RS_C64 = 0, RS_C128 = 1 } rs_dtype; /* interleaved (re, im) */
  *                         psi -= beta m / M
  *   RS_MODEL_INTRA_CHIRP  Doppler shift within the chirp, with the sign of
  *                         the slow-time term: b -= v (2 fc / (c0 Fs))
+ * and one changes the strength instead:
+ *   RS_MODEL_BLOCK_STRENGTH  eq. (1)'s sigma_{m,n,l} varies with the TDM
+ *                         block l (the same for every channel): a_p becomes
+ *                         a_{p,l}, and rs_pixels.amp points to float32
+ *                         [L][P], the strength of pixel p in block l at
+ *                         amp[l * P + p] (L * P values per frame).
  * Range migration over the CPI is not modelled by any variant. */
 typedef enum {
     RS_MODEL_FAR_FIELD = 1,
     RS_MODEL_TDM_SLOT = 2,
     RS_MODEL_INTRA_CHIRP = 4,
-    RS_MODEL_RVP = 8
+    RS_MODEL_RVP = 8,
+    RS_MODEL_BLOCK_STRENGTH = 16
 } rs_model_flags;
 
 /* eq. (1) signal model, SI units.  tx_xyz / rx_xyz are HOST arrays
@@ -109,7 +117,10 @@ typedef struct {
     int32_t model;           /* rs_model_flags, 0 = eq. (1) as above            */
 } rs_radar;
 
-/* One frame of rendered pixels, caller-owned DEVICE pointers, float32 SoA. */
+/* One frame of rendered pixels, caller-owned DEVICE pointers, float32 SoA:
+ * x, y, z, vr hold P values; amp holds P values, or L * P ([L][P]) when the
+ * plan's model has RS_MODEL_BLOCK_STRENGTH.  Array lengths cannot be
+ * checked: shorter arrays are read out of bounds. */
 typedef struct {
     int64_t P; /* >= 0; pointers may be NULL when P == 0 */
     const float *x, *y, *z, *amp, *vr;

@@ -95,6 +95,7 @@ rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *par
     j.Kf = pl->Kf;
     j.Krvp = pl->Krvp;
     j.model = pl->model;
+    j.amp_lstride = (pl->model & RS_MODEL_BLOCK_STRENGTH) ? px->P : 0;
     j.M = pl->M;
     j.N = pl->N;
     j.Ns = pl->Ns;
@@ -113,9 +114,9 @@ rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *par
     return j;
 }
 
-rs_status rs_launch_scale_checked(const rs_launch &L, hipStream_t st)
+rs_status rs_launch_scale_checked(const rs_launch &L, bool block_strength, hipStream_t st)
 {
-    rs_launch_chunk_scale(L, st);
+    rs_launch_chunk_scale(L, block_strength, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "chunk-scale launch: %s", hipGetErrorString(e));
     return RS_OK;
@@ -191,7 +192,7 @@ extern "C" void rs_kernel_timer_destroy(rs_kernel_timer *t)
     delete t;
 }
 
-rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, int grid, hipStream_t st)
+rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, bool block_strength, int grid, hipStream_t st)
 {
     if (L.total <= 0) return RS_OK;
     rs_kernel_timer *tm = tl_timer;
@@ -200,7 +201,7 @@ rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, int grid, hipStr
     if (pl->form == RS_FORM_FP64_DIRECT)
         rs_launch_plain(L, pl->tl, grid, st);
     else
-        rs_launch_mfma(L, pl->wn, pl->tl, pl->nw, grid, st);
+        rs_launch_mfma(L, pl->wn, pl->tl, pl->nw, block_strength, grid, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "main kernel launch: %s", hipGetErrorString(e));
     if (timed) {
@@ -241,7 +242,8 @@ extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtyp
     if (form != RS_FORM_FP64_DIRECT && form != RS_FORM_MFMA_SPLIT16)
         return rs_fail(RS_E_INVALID, "unknown form");
     if (dtype != RS_C64 && dtype != RS_C128) return rs_fail(RS_E_INVALID, "unknown dtype");
-    if (r->model < 0 || (r->model & ~(RS_MODEL_FAR_FIELD | RS_MODEL_TDM_SLOT | RS_MODEL_INTRA_CHIRP | RS_MODEL_RVP)))
+    if (r->model < 0 || (r->model & ~(RS_MODEL_FAR_FIELD | RS_MODEL_TDM_SLOT | RS_MODEL_INTRA_CHIRP | RS_MODEL_RVP |
+                                      RS_MODEL_BLOCK_STRENGTH)))
         return rs_fail(RS_E_INVALID, "unknown model flags 0x%x", (unsigned)r->model);
     if (max_pixels < 0) return rs_fail(RS_E_INVALID, "max_pixels < 0");
     if (max_pixels > ((int64_t)1 << 40)) return rs_fail(RS_E_INVALID, "max_pixels too large");
@@ -414,10 +416,11 @@ extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, voi
     if (pl->form == RS_FORM_MFMA_SPLIT16 && S > 0) {
         rs_launch Sc = L;
         Sc.total = S;
-        if ((s = rs_launch_scale_checked(Sc, st)) != RS_OK) return s;
+        if ((s = rs_launch_scale_checked(Sc, (pl->model & RS_MODEL_BLOCK_STRENGTH) != 0, st)) != RS_OK) return s;
     }
     L.total = L.inline_job.item_count;
-    if ((s = rs_launch_main(pl, L, (int)L.total, st)) != RS_OK) return s;
+    if ((s = rs_launch_main(pl, L, (pl->model & RS_MODEL_BLOCK_STRENGTH) != 0, (int)L.total, st)) != RS_OK)
+        return s;
     rs_launch R = L;
     R.total = (int64_t)pl->C * pl->L * pl->Ns;
     R.counter = nullptr;
@@ -509,13 +512,13 @@ extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *fram
         rs_launch Sc = L;
         Sc.counter = nullptr;
         Sc.total = chunks;
-        s = rs_launch_scale_checked(Sc, st);
+        s = rs_launch_scale_checked(Sc, (pl->model & RS_MODEL_BLOCK_STRENGTH) != 0, st);
     }
     if (s == RS_OK && items > 0) {
         rs_launch_zero_int(L.counter, 1, st);
         int64_t grid = (int64_t)pl->ncu * pl->occupancy;
         if (grid > items) grid = items;
-        s = rs_launch_main(pl, L, (int)grid, st);
+        s = rs_launch_main(pl, L, (pl->model & RS_MODEL_BLOCK_STRENGTH) != 0, (int)grid, st);
     }
     if (s == RS_OK) {
         rs_launch R = L;

@@ -47,9 +47,10 @@ rs_status rs_plan_chunking(const rs_plan *pl, int64_t P, int32_t *S, int32_t *ch
 size_t rs_partial_bytes(const rs_plan *pl, int32_t S);
 size_t rs_workspace_bytes(const rs_plan *pl, int32_t S);   // partials + chunk scales
 int32_t rs_steps_per_chunk(const rs_plan *pl, int32_t chunk);
-rs_status rs_launch_scale_checked(const rs_launch &L, hipStream_t st);
+rs_status rs_launch_scale_checked(const rs_launch &L, bool block_strength, hipStream_t st);
 rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *partial,
                    int32_t S, int32_t chunk);
 rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px);
-rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, int grid, hipStream_t st);
+// block_strength: some job of the launch has strengths per block
+rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, bool block_strength, int grid, hipStream_t st);
 rs_status rs_launch_reduce_checked(const rs_plan *pl, const rs_launch &L, hipStream_t st);

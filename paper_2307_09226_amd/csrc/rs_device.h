@@ -17,6 +17,16 @@ __device__ __forceinline__ double rs_distance(float x, float y, float z, const d
     return __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
 }
 
+// Load p[i] from global memory.  Device pointers read out of a job table
+// are generic (flat) to the compiler; a flat load also counts against the
+// LDS wait counter, so a kernel waiting on its LDS operands would wait for
+// the global load too.  Caller arrays are always global memory.
+template <typename T>
+__device__ __forceinline__ T rs_gload(const T *p, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+
 // Fractional part v - floor(v), in [0, 1] (1 only by rounding of tiny
 // negative v).
 __device__ __forceinline__ double rs_frac(double v) { return v - __builtin_floor(v); }
@@ -26,8 +36,10 @@ __device__ __forceinline__ double rs_frac(double v) { return v - __builtin_floor
 // frequency (cycles per fast-time sample), beta the Doppler phase per block
 // (cycles).  Without variant flags R = (|x - tx_m| + |x - rx_r|) / 2,
 // psi = R Kc, b = R Kb, beta = v Kd.  The flags (rs_model_flags) change psi
-// and b in the order below.
-__device__ __forceinline__ void rs_chan_args(const rs_job &J, float x, float y, float z, float v, int m,
+// and b in the order below.  J: an rs_job or any struct with its constants
+// (model, M, Kc, Kb, Kd, Kf, Krvp).
+template <typename JobConsts>
+__device__ __forceinline__ void rs_chan_args(const JobConsts &J, float x, float y, float z, float v, int m,
                                              const double *tx, const double *rx, double *psi, double *b,
                                              double *beta)
 {

@@ -26,6 +26,7 @@ struct rs_job {
     int32_t seg_begin, seg_end;  // 16-pixel steps of every chunk covered by this launch
     int32_t dtype;             // 0 = complex64, 1 = complex128
     int32_t model;             // signal-model variant flags (rs_model_flags)
+    int64_t amp_lstride;       // P when strengths vary over the blocks (amp[l * P + p]), else 0
 };
 
 // Job table of one launch.  With jobs == nullptr the single job `inline_job`
@@ -84,8 +85,10 @@ __device__ __forceinline__ rs_item rs_decode_item(const rs_job &J, int64_t local
 
 // Kernel entry points (defined in the .hip files, launched by rs_api.hip).
 void rs_launch_plain(const rs_launch &L, int tl, int grid, hipStream_t st);
-void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, int grid, hipStream_t st);
+// block_strength: some job of the launch has amp_lstride != 0
+void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, bool block_strength, int grid, hipStream_t st);
 bool rs_mfma_shape_supported(int wn, int tl, int nw);
 void rs_launch_reduce(const rs_launch &L, int form, hipStream_t st);
-void rs_launch_chunk_scale(const rs_launch &L, hipStream_t st);
+// block_strength: some job of the launch has strengths per block
+void rs_launch_chunk_scale(const rs_launch &L, bool block_strength, hipStream_t st);
 void rs_launch_zero_int(int *p, int n, hipStream_t st);

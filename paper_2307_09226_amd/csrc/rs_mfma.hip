@@ -36,6 +36,14 @@
 // its relative precision for the small ones; the partial sum is scaled back
 // exactly when it is written.
 //
+// Strengths per block (BS = true, jobs with amp_lstride != 0): D[p][l] =
+// a_{p,l} exp(-j2pi beta_p l) is still one shared matrix per pixel chunk, so
+// only its evaluation changes: the rotated phasor carries the chunk scale
+// alone and each D entry is multiplied by its strength, read from global
+// memory at the start of the step before it.  Jobs without per-block
+// strengths in the same launch multiply by 1 (exact), so their cubes keep
+// the bits of the launch without BS.
+//
 // Segments: a launch may cover only steps [seg_begin, seg_end) of every
 // chunk.  The raw fp32 accumulators are then parked in the partial buffer
 // and reloaded by the next segment, which makes the result independent of
@@ -106,10 +114,22 @@ __device__ __forceinline__ void rot(float &u, float &w, float rx, float ry)
 }
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Per-item constants of the phase-argument recipe and the pixel arrays,
+// copied to LDS once per work item: the job table is generic memory to the
+// compiler, which reloads its fields after every LDS store (they might
+// alias) and waits for each such load.
+struct item_consts {
+    double Kc, Kb, Kd, Kf, Krvp;
+    double tx[3], rx[3];            // antennas of the item's channel
+    const float *x, *y, *z, *amp, *vr;
+    int64_t amp_lstride;
+    int32_t model, M, L, pad_;
+};
 typedef std::integral_constant<int, 0> buf0_t;
 typedef std::integral_constant<int, 1> buf1_t;
 
-template <int WN, int TL, int NW, bool PHASE>
+template <int WN, int TL, int NW, bool PHASE, bool BS>
 __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
 {
     constexpr int NT = 64 * NW;          // threads per workgroup
@@ -126,6 +146,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
     __shared__ __align__(16) char sD0[2][DBYTES];  // [hi, lo]
     __shared__ __align__(16) char sD1[2][DBYTES];
     __shared__ pix_par sPar[2][kPB];
+    __shared__ item_consts sK;
     __shared__ int64_t sItem;
 
     const int tid = threadIdx.x;
@@ -151,24 +172,48 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         const bool seg_first = k0 == 0, seg_last = k1 == nsteps;
         const bool full_tile = n0 + TN <= J.Ns && l0 + TL <= J.L;
         const int m = it.c / J.N, r = it.c % J.N;
-        const double *tx = J.ant + 3 * m;
-        const double *rx = J.ant + 3 * (J.M + r);
         const int sh = J.scale[it.s];
         const float a_scale = ldexpf(1.0f, sh);
+        const bool per_block = BS && J.amp_lstride != 0;
+        // every reader of the previous item's sK has passed a barrier since
+        if (tid == 0) {
+            item_consts k;
+            k.Kc = J.Kc;
+            k.Kb = J.Kb;
+            k.Kd = J.Kd;
+            k.Kf = J.Kf;
+            k.Krvp = J.Krvp;
+            for (int i = 0; i < 3; ++i) {
+                k.tx[i] = J.ant[3 * m + i];
+                k.rx[i] = J.ant[3 * (J.M + r) + i];
+            }
+            k.x = J.x;
+            k.y = J.y;
+            k.z = J.z;
+            k.amp = J.amp;
+            k.vr = J.vr;
+            k.amp_lstride = J.amp_lstride;
+            k.model = J.model;
+            k.M = J.M;
+            k.L = J.L;
+            k.pad_ = 0;
+            sK = k;
+        }
 
         // ---- pixel parameter blocks (256 pixels), raw data prefetched one
-        // block ahead so that the global-memory latency stays hidden --------
-        float rxp = 0.f, ryp = 0.f, rzp = 0.f, rap = 0.f, rvp = 0.f;
+        // block ahead so that the global-memory latency stays hidden.  The
+        // loads are unconditional (index clamped into the chunk) and their
+        // validity is decided when the block is used: a conditional zero
+        // would make the compiler wait for the loads right away. ----------
+        float rxp, ryp, rzp, rap, rvp;
         auto fetch_block = [&](int blk) {
-            const int64_t p = pb + (int64_t)blk * kPB + tid;
-            if (tid < kPB && blk < nblocks && p < pe) {
-                rxp = J.x[p];
-                ryp = J.y[p];
-                rzp = J.z[p];
-                rap = J.amp[p];
-                rvp = J.vr[p];
-            } else {
-                rxp = ryp = rzp = rap = rvp = 0.f;
+            if (tid < kPB) {
+                const int64_t p = min(pb + (int64_t)blk * kPB + tid, pe - 1);
+                rxp = rs_gload(sK.x, p);
+                ryp = rs_gload(sK.y, p);
+                rzp = rs_gload(sK.z, p);
+                rap = rs_gload(sK.amp, p);
+                rvp = rs_gload(sK.vr, p);
             }
         };
         auto load_block = [&](int blk) {
@@ -177,9 +222,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 pix_par q;
                 if (p < pe) {
                     double psi;
-                    rs_chan_args(J, rxp, ryp, rzp, rvp, m, tx, rx, &psi, &q.b, &q.beta);
+                    rs_chan_args(sK, rxp, ryp, rzp, rvp, m, sK.tx, sK.rx, &psi, &q.b, &q.beta);
                     q.psi_f = rs_frac(psi);
-                    q.a = rap * a_scale;
+                    q.a = per_block ? a_scale : rap * a_scale;
                 } else {
                     q.psi_f = 0.0;
                     q.b = 0.0;
@@ -208,8 +253,26 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         // Thread: pixel q, blocks l = l0 + lq + LQ k; D = u - j w with
         // u + j w = a exp(j2pi beta l); real column (u, w), imaginary (-w, u).
         auto d_column = [](int k) { return ((LQ * k) >> 5) * 64 + ((LQ * k) & 31); };
+        // strengths of this thread's D entries of step st (1 where the job
+        // has none per block, or the pixel or block lies past the end)
+        auto load_al = [&](int st, float (&al)[DPT]) {
+            const int64_t p = pb + (int64_t)st * kKP + q;
+#pragma unroll
+            for (int k = 0; k < DPT; ++k) {
+                const int l = l0 + lq + LQ * k;
+                al[k] = per_block && p < pe && l < sK.L ? rs_gload(sK.amp, p + (int64_t)l * sK.amp_lstride) : 1.0f;
+            }
+        };
+        // D entry (u, w) times its strength, pinned
+        auto scaled = [&](float u, float w, float a, float &su, float &sw) {
+            su = u * a;
+            sw = w * a;
+            pin(su, sw);
+        };
         auto gen_d = [&](int st, auto dbuf) {
             const pix_par &pp = sPar[(st / kSPB) & 1][(st % kSPB) * kKP + q];
+            float al[DPT];
+            if constexpr (BS) load_al(st, al);
             const float f = frac32(pp.beta * (double)(l0 + lq));  // binary64 reduction
             float u = pp.a * __builtin_amdgcn_cosf(f);
             float w = pp.a * __builtin_amdgcn_sinf(f);
@@ -219,8 +282,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             char *dl = db[1] + lq * kCS + q * 4;
 #pragma unroll
             for (int k = 0; k < DPT; ++k) {
-                const half2v hre = hi2(u, w), him = hi2(-w, u);
-                const half2v lre = lo2(u, w, hre), lim = lo2(-w, u, him);
+                float su = u, sw = w;
+                if constexpr (BS) scaled(u, w, al[k], su, sw);
+                const half2v hre = hi2(su, sw), him = hi2(-sw, su);
+                const half2v lre = lo2(su, sw, hre), lim = lo2(-sw, su, him);
                 const int cre = d_column(k) * kCS, cim = cre + 32 * kCS;
                 *reinterpret_cast<unsigned *>(dh + cre) = bits(hre);
                 *reinterpret_cast<unsigned *>(dh + cim) = bits(him);
@@ -309,6 +374,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         auto step = [&](int st, auto cur, auto nxt, const fops &fc, fops &fn, int fstep) {
             if ((st % kSPB) == 0 && st / kSPB + 1 < nblocks) load_block(st / kSPB + 1);
             const int s1 = st + 1;
+            float al[DPT];
+            if constexpr (BS) load_al(s1, al);
             const pix_par &pd = sPar[(s1 / kSPB) & 1][(s1 % kSPB) * kKP + q];
             const float fd = frac32(pd.beta * (double)(l0 + lq));
             float u = pd.a * __builtin_amdgcn_cosf(fd);
@@ -348,8 +415,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             };
             auto valu_slice = [&](int gi) {
                 if (gi < DPT) {
-                    const half2v hre = hi2(u, w), him = hi2(-w, u);
-                    const half2v lre = lo2(u, w, hre), lim = lo2(-w, u, him);
+                    float su = u, sw = w;
+                    if constexpr (BS) scaled(u, w, al[gi], su, sw);
+                    const half2v hre = hi2(su, sw), him = hi2(-sw, su);
+                    const half2v lre = lo2(su, sw, hre), lim = lo2(-sw, su, him);
                     const int cre = d_column(gi) * kCS, cim = cre + 32 * kCS;
                     *reinterpret_cast<unsigned *>(dwh + cre) = bits(hre);
                     *reinterpret_cast<unsigned *>(dwh + cim) = bits(him);
@@ -366,9 +435,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             };
             if (kShift && wave >= 4) {
                 // second wave of each SIMD: phasor work first, then the
-                // matrix work, so that it complements the first wave
+                // matrix work, so that it complements the first wave (with
+                // strengths per block the F slices go first, giving the
+                // strength loads time to arrive)
 #pragma unroll
-                for (int gi = 0; gi < NG; ++gi) valu_slice(gi);
+                for (int i = 0; i < NG; ++i) valu_slice(BS ? (i + DPT) % NG : i);
                 __builtin_amdgcn_sched_barrier(0);
                 mfma_prologue();
 #pragma unroll
@@ -459,8 +530,51 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
     }
 }
 
+// Largest |a| over 256 threads (every thread gets it).
+__device__ __forceinline__ float block_max(float am, float *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) am = fmaxf(am, __shfl_xor(am, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = am;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// Row groups of the strengths-per-block maximum: block l belongs to group
+// l mod G.  G <= L keeps the G floats per chunk inside the chunk's share of
+// the partial-sum buffer (C L Ns complex entries).
+__device__ __forceinline__ int row_groups(const rs_job &J) { return min(16, J.L); }
+
+// Strengths per block: the maximum of |a_{p,l}| over the pixels of a chunk
+// and the blocks of one row group (blockIdx.y), written to the job's
+// partial-sum buffer, which the main kernel overwrites only later.  Jobs
+// without strengths per block are skipped.
+__global__ __launch_bounds__(256) void k_chunk_rowmax(rs_launch Lc)
+{
+    __shared__ float red[4];
+    const int64_t gch = blockIdx.x;
+    if (gch >= Lc.total) return;
+    const int jidx = rs_find_job<RS_BY_CHUNK>(Lc, gch);
+    const rs_job &J = rs_job_of(Lc, jidx);
+    const int G = row_groups(J);
+    const int grp = blockIdx.y;
+    if (J.amp_lstride == 0 || grp >= G) return;
+    const int s = (int)(gch - J.chunk_begin);
+    const int64_t pb = (int64_t)s * J.chunk;
+    const int64_t pe = min(J.P, pb + (int64_t)J.chunk);
+    float am = 0.f;
+    for (int l = grp; l < J.L; l += G) {
+        const float *a = J.amp + (int64_t)l * J.amp_lstride;
+        for (int64_t p = pb + threadIdx.x; p < pe; p += 256) am = fmaxf(am, fabsf(rs_gload(a, p)));
+    }
+    am = block_max(am, red);
+    if (threadIdx.x == 0) reinterpret_cast<float *>(J.partial)[(int64_t)s * G + grp] = am;
+}
+
 // Per-chunk strength scale: sh = 14 - floor(log2(max |a|)) so that the
-// largest scaled strength of the chunk lies in [2^14, 2^15).
+// largest scaled strength of the chunk (over all blocks when strengths vary
+// per block: the row-group maxima left by k_chunk_rowmax) lies in
+// [2^14, 2^15).
 __global__ __launch_bounds__(256) void k_chunk_scale(rs_launch Lc)
 {
     __shared__ float red[4];
@@ -472,13 +586,14 @@ __global__ __launch_bounds__(256) void k_chunk_scale(rs_launch Lc)
     const int64_t pb = (int64_t)s * J.chunk;
     const int64_t pe = min(J.P, pb + (int64_t)J.chunk);
     float am = 0.f;
-    for (int64_t p = pb + threadIdx.x; p < pe; p += 256) am = fmaxf(am, fabsf(J.amp[p]));
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) am = fmaxf(am, __shfl_xor(am, o));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = am;
-    __syncthreads();
+    if (J.amp_lstride) {
+        const int G = row_groups(J);
+        if ((int)threadIdx.x < G) am = reinterpret_cast<const float *>(J.partial)[(int64_t)s * G + threadIdx.x];
+    } else {
+        for (int64_t p = pb + threadIdx.x; p < pe; p += 256) am = fmaxf(am, fabsf(J.amp[p]));
+    }
+    am = block_max(am, red);
     if (threadIdx.x == 0) {
-        am = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
         int ex = (am > 0.f && am <= 3.4e38f) ? ilogbf(am) : kAmpExp;
         int sh = kAmpExp - ex;
         J.scale[s] = sh > 126 ? 126 : (sh < -126 ? -126 : sh);
@@ -495,13 +610,29 @@ bool phase_enabled()
     return on;
 }
 
-template <int WN, int TL, int NW>
+template <int WN, int TL, int NW, bool BS>
 void launch_one(const rs_launch &L, int grid, hipStream_t st)
 {
     if (NW == 8 && phase_enabled())
-        hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, true>), dim3(grid), dim3(64 * NW), 0, st, L);
+        hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, true, BS>), dim3(grid), dim3(64 * NW), 0, st, L);
     else
-        hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, false>), dim3(grid), dim3(64 * NW), 0, st, L);
+        hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, false, BS>), dim3(grid), dim3(64 * NW), 0, st, L);
+}
+
+template <bool BS>
+void launch_shape(const rs_launch &L, int wn, int tl, int nw, int grid, hipStream_t st)
+{
+    if (tl == 128) {
+        if (wn == 64) launch_one<64, 128, 4, BS>(L, grid, st);
+        else if (nw == 8) launch_one<32, 128, 8, BS>(L, grid, st);
+        else launch_one<32, 128, 4, BS>(L, grid, st);
+    } else {
+        if (wn == 32 && nw == 8) launch_one<32, 64, 8, BS>(L, grid, st);
+        else if (wn == 32) launch_one<32, 64, 4, BS>(L, grid, st);
+        else if (wn == 64 && nw == 8) launch_one<64, 64, 8, BS>(L, grid, st);
+        else if (wn == 64) launch_one<64, 64, 4, BS>(L, grid, st);
+        else launch_one<128, 64, 4, BS>(L, grid, st);
+    }
 }
 
 }  // namespace
@@ -514,23 +645,17 @@ bool rs_mfma_shape_supported(int wn, int tl, int nw)
                          (wn == 128 && nw == 4)));
 }
 
-void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, int grid, hipStream_t st)
+void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, bool block_strength, int grid, hipStream_t st)
 {
-    if (tl == 128) {
-        if (wn == 64) launch_one<64, 128, 4>(L, grid, st);
-        else if (nw == 8) launch_one<32, 128, 8>(L, grid, st);
-        else launch_one<32, 128, 4>(L, grid, st);
-    } else {
-        if (wn == 32 && nw == 8) launch_one<32, 64, 8>(L, grid, st);
-        else if (wn == 32) launch_one<32, 64, 4>(L, grid, st);
-        else if (wn == 64 && nw == 8) launch_one<64, 64, 8>(L, grid, st);
-        else if (wn == 64) launch_one<64, 64, 4>(L, grid, st);
-        else launch_one<128, 64, 4>(L, grid, st);
-    }
+    if (block_strength)
+        launch_shape<true>(L, wn, tl, nw, grid, st);
+    else
+        launch_shape<false>(L, wn, tl, nw, grid, st);
 }
 
-void rs_launch_chunk_scale(const rs_launch &L, hipStream_t st)
+void rs_launch_chunk_scale(const rs_launch &L, bool block_strength, hipStream_t st)
 {
     if (L.total <= 0) return;
+    if (block_strength) hipLaunchKernelGGL(k_chunk_rowmax, dim3((unsigned)L.total, 16), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_chunk_scale, dim3((unsigned)L.total), dim3(256), 0, st, L);
 }

@@ -13,7 +13,9 @@
 // binary64 accumulators.  A thread evaluates a run of consecutive phasors of
 // one pixel: the first directly (binary64 sincospi of the reduced phase),
 // the others by binary64 rotation with exp(j2pi frac(b)) or
-// exp(-j2pi frac(beta)), at most 7 rotations (~1e-15 relative).  Chunks
+// exp(-j2pi frac(beta)), at most 7 rotations (~1e-15 relative).  With
+// strengths per block (amp_lstride != 0) the slow-time run rotates the unit
+// phasor and multiplies each entry by a_{p,l}.  Chunks
 // write binary64 partial tiles that the reduce kernel sums in a fixed
 // order.
 #include "rs_device.h"
@@ -98,14 +100,30 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
                 double ds, dc, ts, tc;
                 sincospi(2.0 * rs_frac(beta * (double)(l0 + DR * r)), &ds, &dc);
                 sincospi(2.0 * rs_frac(beta), &ts, &tc);
-                dc *= a;
-                ds *= a;
+                if (J.amp_lstride == 0) {
+                    dc *= a;
+                    ds *= a;
 #pragma unroll
-                for (int k = 0; k < DR; ++k) {
-                    sD[q][DR * r + k] = make_double2(dc, -ds);
-                    const double cn = __builtin_fma(dc, tc, -(ds * ts));
-                    ds = __builtin_fma(dc, ts, ds * tc);
-                    dc = cn;
+                    for (int k = 0; k < DR; ++k) {
+                        sD[q][DR * r + k] = make_double2(dc, -ds);
+                        const double cn = __builtin_fma(dc, tc, -(ds * ts));
+                        ds = __builtin_fma(dc, ts, ds * tc);
+                        dc = cn;
+                    }
+                } else {
+                    // strength per block: the unit phasor is rotated and
+                    // each entry multiplied by a_{p,l}
+                    const int64_t p = p0 + q;
+#pragma unroll
+                    for (int k = 0; k < DR; ++k) {
+                        const int l = l0 + DR * r + k;
+                        const double al =
+                            p < pe && l < J.L ? (double)J.amp[p + (int64_t)l * J.amp_lstride] : 0.0;
+                        sD[q][DR * r + k] = make_double2(dc * al, -(ds * al));
+                        const double cn = __builtin_fma(dc, tc, -(ds * ts));
+                        ds = __builtin_fma(dc, ts, ds * tc);
+                        dc = cn;
+                    }
                 }
             }
             __syncthreads();

@@ -227,12 +227,14 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
     // chunk-scale jobs
     const int js = nj;
     int64_t chunks = 0;
+    bool scale_bs = false;  // some new request has strengths per block
     for (const auto &p : parts) {
         if (!p.scale) continue;
         rs_job j = rs_make_job(p.r->plan, &p.r->px, p.r->cube, s->arena + p.r->arena_off, p.r->S,
                                p.r->chunk);
         j.chunk_begin = chunks;
         chunks += p.r->S;
+        if (j.amp_lstride) scale_bs = true;
         rg.h_jobs[nj++] = j;
     }
     const int nscale = nj - js;
@@ -241,13 +243,14 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
         int wn, tl, nw, j0, n;
         int64_t items;
         const rs_plan *pl;
+        bool block_strength;  // some request of the group has strengths per block
     };
     std::vector<group> groups;
     for (const auto &p : parts) {
         bool found = false;
         for (auto &g : groups)
             if (g.wn == p.r->plan->wn && g.tl == p.r->plan->tl && g.nw == p.r->plan->nw) found = true;
-        if (!found) groups.push_back(group{p.r->plan->wn, p.r->plan->tl, p.r->plan->nw, 0, 0, 0, p.r->plan});
+        if (!found) groups.push_back(group{p.r->plan->wn, p.r->plan->tl, p.r->plan->nw, 0, 0, 0, p.r->plan, false});
     }
     for (auto &g : groups) {
         g.j0 = nj;
@@ -261,6 +264,7 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
             j.seg_begin = p.seg_begin;
             j.seg_end = p.seg_end;
             g.items += p.r->items;
+            if (j.amp_lstride) g.block_strength = true;
             rg.h_jobs[nj++] = j;
         }
         g.n = nj - g.j0;
@@ -285,7 +289,7 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
         Sc.jobs = rg.d_jobs + js;
         Sc.njobs = nscale;
         Sc.total = chunks;
-        if (rs_launch_scale_checked(Sc, s->stream) != RS_OK) return hipErrorLaunchFailure;
+        if (rs_launch_scale_checked(Sc, scale_bs, s->stream) != RS_OK) return hipErrorLaunchFailure;
     }
     int launch = 0;
     for (auto &g : groups) {
@@ -298,7 +302,7 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
         L.counter = rg.d_counter + launch++;
         rs_launch_zero_int(L.counter, 1, s->stream);
         const int64_t grid = std::min<int64_t>(g.items, (int64_t)s->ncu * g.pl->occupancy);
-        if (rs_launch_main(g.pl, L, (int)grid, s->stream) != RS_OK) return hipErrorLaunchFailure;
+        if (rs_launch_main(g.pl, L, g.block_strength, (int)grid, s->stream) != RS_OK) return hipErrorLaunchFailure;
     }
     if (nred > 0) {
         rs_launch R;

@@ -21,6 +21,7 @@ RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_UNSUPPORTED, RS_E_BUSY, RS_E_
 RS_FORM_FP64_DIRECT, RS_FORM_MFMA_SPLIT16 = 0, 1
 RS_C64, RS_C128 = 0, 1
 RS_REQ_QUEUED, RS_REQ_RUNNING, RS_REQ_DONE, RS_REQ_FAILED, RS_REQ_CANCELLED = range(5)
+RS_MODEL_FAR_FIELD, RS_MODEL_TDM_SLOT, RS_MODEL_INTRA_CHIRP, RS_MODEL_RVP, RS_MODEL_BLOCK_STRENGTH = 1, 2, 4, 8, 16
 STATUS_NAMES = {0: "RS_OK", 1: "RS_E_INVALID", 2: "RS_E_NOMEM", 3: "RS_E_DEVICE",
                 4: "RS_E_UNSUPPORTED", 5: "RS_E_BUSY", 6: "RS_E_NOT_FOUND"}
 
@@ -174,17 +175,26 @@ class DevicePixels:
 
     @classmethod
     def from_host(cls, px, device="cuda:0") -> "DevicePixels":
+        """amp may be [P] or, for plans with RS_MODEL_BLOCK_STRENGTH, [L][P]."""
         import torch
         arrs = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
                 for a in (px.x, px.y, px.z, px.amp, px.vr)]
         return cls(*arrs)
 
-    def struct(self) -> rs_pixels:
+    def struct(self, plan: Optional["Plan"] = None) -> rs_pixels:
+        """C view of the arrays.  With a plan, amp must hold L * P values when
+        the plan's model has RS_MODEL_BLOCK_STRENGTH and P otherwise."""
         if self.P == 0:
             return rs_pixels(0, None, None, None, None, None)
-        for a in (self.x, self.y, self.z, self.amp, self.vr):
-            if a.numel() != self.P or not a.is_contiguous() or str(a.dtype) != "torch.float32":
-                raise ValueError("pixel arrays must be contiguous float32 of equal length")
+        rows = 1
+        if plan is not None and int(getattr(plan.radar, "model", 0)) & RS_MODEL_BLOCK_STRENGTH:
+            rows = int(plan.radar.L)
+        for i, a in enumerate((self.x, self.y, self.z, self.amp, self.vr)):
+            want = self.P * (rows if i == 3 else 1)
+            if i == 3 and plan is None and a.numel() % self.P == 0:
+                want = a.numel()
+            if a.numel() != want or not a.is_contiguous() or str(a.dtype) != "torch.float32":
+                raise ValueError(f"pixel array {i}: {a.numel()} contiguous float32 values, expected {want}")
         return rs_pixels(self.P, _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.amp),
                          _ptr(self.vr))
 
@@ -258,14 +268,14 @@ def new_cube(plan: Plan, device="cuda:0", count: Optional[int] = None):
 
 
 def rs_beat_synthesize(plan: Plan, pixels: DevicePixels, cube, stream=None):
-    ps = pixels.struct()
+    ps = pixels.struct(plan)
     _check(lib.rs_beat_synthesize(plan.handle, ctypes.byref(ps), _ptr(cube),
                                   _stream_handle(stream)))
     return cube
 
 
 def rs_beat_synthesize_ws(plan: Plan, pixels: DevicePixels, cube, workspace, stream=None):
-    ps = pixels.struct()
+    ps = pixels.struct(plan)
     nbytes = workspace.numel() * workspace.element_size()
     _check(lib.rs_beat_synthesize_ws(plan.handle, ctypes.byref(ps), _ptr(cube),
                                      _ptr(workspace) if nbytes else None, nbytes,
@@ -343,7 +353,7 @@ def rs_render_scenes(scenes_, g_az: int, g_el: int, noise=None, device="cuda:0",
 def rs_beat_synthesize_batch(plan: Plan, frames: Sequence[DevicePixels], cubes, stream=None):
     arr = (rs_pixels * max(1, len(frames)))()
     for i, f in enumerate(frames):
-        arr[i] = f.struct()
+        arr[i] = f.struct(plan)
     _check(lib.rs_beat_synthesize_batch(plan.handle, arr, len(frames), _ptr(cubes),
                                         _stream_handle(stream)))
     return cubes
@@ -362,7 +372,7 @@ class Session:
         self._keep = {}
 
     def submit(self, plan: Plan, pixels: DevicePixels, cube) -> int:
-        ps = pixels.struct()
+        ps = pixels.struct(plan)
         t = ctypes.c_uint64()
         _check(lib.rs_session_submit(self.handle, plan.handle, ctypes.byref(ps), _ptr(cube),
                                      ctypes.byref(t)))

@@ -45,7 +45,7 @@ def test_invalid_plan_arguments_rejected_on_host():
     r = scenes.radar_small()
     bad = [
         dict(M=0), dict(N=0), dict(Ns=0), dict(L=0), dict(Fs=0.0), dict(Tb=-1.0),
-        dict(c0=0.0), dict(fc=float("nan")), dict(mu=float("inf")), dict(model=16), dict(model=-1),
+        dict(c0=0.0), dict(fc=float("nan")), dict(mu=float("inf")), dict(model=32), dict(model=-1),
     ]
     for kw in bad:
         rr = scenes.Radar(**{**r.__dict__, **kw})

@@ -71,7 +71,7 @@ def test_variants_change_the_cube_and_batch_is_bitwise():
 def test_unknown_model_flags_rejected():
     import ctypes
     rs = _rs()
-    r = dataclasses.replace(scenes.radar_small(), model=16)
+    r = dataclasses.replace(scenes.radar_small(), model=32)
     st, keep = rs._radar_struct(r)
     h = ctypes.c_void_p()
     assert rs.lib.rs_cube_plan(ctypes.byref(st), 1, 0, 10, ctypes.byref(h)) == rs.RS_E_INVALID
