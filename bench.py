@@ -68,7 +68,7 @@ def parse():
                     help="untimed steps first; the clock takes ~50 steps (~25 ms) of load to settle")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline single-frame measurement")
-    ap.add_argument("--legs", default="plain,batch,doppler_time,serving,cpu",
+    ap.add_argument("--legs", default="plain,variants,batch,doppler_time,serving,cpu",
                     help="extra legs after the headline (comma-separated subset)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
@@ -222,6 +222,30 @@ def main():
         }
         out["mfma_speedup_vs_plain"] = out["value"] / out["plain_fp64"]["terms_per_s"]
         pplan.close()
+
+    if "variants" in legs:
+        # ---- signal-model variants on the same frame (matrix-core form) -----------
+        import dataclasses
+        out["variants"] = {"workload": "the headline frame with model flags", "models": {}}
+        for model, name in ((15, "far field + Tx slot + intra-chirp Doppler + RVP"),
+                            (16, "strength per block (L x P strengths, 1 +- 0.5 swing)")):
+            vr = dataclasses.replace(radar, model=model)
+            vpx = scenes.block_strengths(px, radar.L, seed=7) if model & 16 else px
+            vplan = rs.rs_cube_plan(vr, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
+            vcube = rs.new_cube(vplan, dev)
+            vdpx = rs.DevicePixels.from_host(vpx, dev) if model & 16 else dpx
+            with timer:
+                vwall, vper = timed_steps(lambda: rs.rs_beat_synthesize(vplan, vdpx, vcube), 20, 20)
+            vk = timer.read()
+            torch.cuda.synchronize()
+            vk_avg = float(np.mean(vk[20:]))
+            out["variants"]["models"][str(model)] = {
+                "name": name, "ms_per_step": vwall * 1e3 / 20, "terms_per_s": terms / (vwall / 20),
+                "kernel_ms": vk_avg, "mfma_frac": FLOP_MFMA * terms / (vk_avg * 1e-3) / PEAK_FP16,
+                "parity": parity_sampled(vr, vpx, vcube.cpu().numpy(), k=128),
+            }
+            del vcube, vdpx
+            vplan.close()
 
     if "batch" in legs:
         # ---- 64 animation frames in one persistent launch -------------------------

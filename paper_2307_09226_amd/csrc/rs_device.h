@@ -63,6 +63,41 @@ __device__ __forceinline__ void rs_chan_args(const JobConsts &J, float x, float 
     if (J.model & 4) *b = *b - (double)v * J.Kf;                          // Doppler within the chirp
 }
 
+// Per-item constants of the phase-argument recipe and the pixel arrays,
+// copied to LDS once per work item by one thread: the job table is generic
+// memory to the compiler, which reloads its fields after every LDS store
+// (they might alias) and waits for each such load.
+struct rs_item_consts {
+    double Kc, Kb, Kd, Kf, Krvp;
+    double tx[3], rx[3];            // antennas of the item's channel (Tx m, Rx r)
+    const float *x, *y, *z, *amp, *vr;
+    int64_t amp_lstride;
+    int32_t model, M, L, pad_;
+};
+
+__device__ __forceinline__ void rs_item_consts_of(const rs_job &J, int m, int r, rs_item_consts &k)
+{
+    k.Kc = J.Kc;
+    k.Kb = J.Kb;
+    k.Kd = J.Kd;
+    k.Kf = J.Kf;
+    k.Krvp = J.Krvp;
+    for (int i = 0; i < 3; ++i) {
+        k.tx[i] = J.ant[3 * m + i];
+        k.rx[i] = J.ant[3 * (J.M + r) + i];
+    }
+    k.x = J.x;
+    k.y = J.y;
+    k.z = J.z;
+    k.amp = J.amp;
+    k.vr = J.vr;
+    k.amp_lstride = J.amp_lstride;
+    k.model = J.model;
+    k.M = J.M;
+    k.L = J.L;
+    k.pad_ = 0;
+}
+
 // Per-pixel quantities of one virtual channel: psi_f = frac(psi), b, beta, a.
 struct rs_pixel_args {
     double psi_f, b, beta;

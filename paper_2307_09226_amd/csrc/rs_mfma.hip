@@ -115,17 +115,6 @@ __device__ __forceinline__ void rot(float &u, float &w, float rx, float ry)
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-// Per-item constants of the phase-argument recipe and the pixel arrays,
-// copied to LDS once per work item: the job table is generic memory to the
-// compiler, which reloads its fields after every LDS store (they might
-// alias) and waits for each such load.
-struct item_consts {
-    double Kc, Kb, Kd, Kf, Krvp;
-    double tx[3], rx[3];            // antennas of the item's channel
-    const float *x, *y, *z, *amp, *vr;
-    int64_t amp_lstride;
-    int32_t model, M, L, pad_;
-};
 typedef std::integral_constant<int, 0> buf0_t;
 typedef std::integral_constant<int, 1> buf1_t;
 
@@ -146,7 +135,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
     __shared__ __align__(16) char sD0[2][DBYTES];  // [hi, lo]
     __shared__ __align__(16) char sD1[2][DBYTES];
     __shared__ pix_par sPar[2][kPB];
-    __shared__ item_consts sK;
+    __shared__ rs_item_consts sK;
     __shared__ int64_t sItem;
 
     const int tid = threadIdx.x;
@@ -176,29 +165,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         const float a_scale = ldexpf(1.0f, sh);
         const bool per_block = BS && J.amp_lstride != 0;
         // every reader of the previous item's sK has passed a barrier since
-        if (tid == 0) {
-            item_consts k;
-            k.Kc = J.Kc;
-            k.Kb = J.Kb;
-            k.Kd = J.Kd;
-            k.Kf = J.Kf;
-            k.Krvp = J.Krvp;
-            for (int i = 0; i < 3; ++i) {
-                k.tx[i] = J.ant[3 * m + i];
-                k.rx[i] = J.ant[3 * (J.M + r) + i];
-            }
-            k.x = J.x;
-            k.y = J.y;
-            k.z = J.z;
-            k.amp = J.amp;
-            k.vr = J.vr;
-            k.amp_lstride = J.amp_lstride;
-            k.model = J.model;
-            k.M = J.M;
-            k.L = J.L;
-            k.pad_ = 0;
-            sK = k;
-        }
+        if (tid == 0) rs_item_consts_of(J, m, r, sK);
 
         // ---- pixel parameter blocks (256 pixels), raw data prefetched one
         // block ahead so that the global-memory latency stays hidden.  The

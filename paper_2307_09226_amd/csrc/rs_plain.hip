@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
     __shared__ double2 sF[kKP][kTN];
     __shared__ double2 sD[kKP][TL];
     __shared__ double sPsi[kKP], sB[kKP], sBeta[kKP], sA[kKP];
+    __shared__ rs_item_consts sK;
     __shared__ int64_t s_item;
 
     const int tid = threadIdx.x;
@@ -48,8 +49,24 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
         const int64_t pb = (int64_t)it.s * J.chunk;
         const int64_t pe = min(J.P, pb + (int64_t)J.chunk);
         const int m = it.c / J.N, r = it.c % J.N;
-        const double *tx = J.ant + 3 * m;
-        const double *rx = J.ant + 3 * (J.M + r);
+        // every reader of the previous item's sK has passed a barrier since
+        if (tid == 0) rs_item_consts_of(J, m, r, sK);
+        __syncthreads();
+        // raw values of this thread's pixel of the next step (threads < kKP),
+        // loaded a step ahead; the index is clamped into the chunk and the
+        // pixel's validity decided when it is used
+        float nx, ny, nz, na, nv;
+        auto fetch = [&](int64_t p0) {
+            if (tid < kKP) {
+                const int64_t p = min(p0 + tid, pe - 1);
+                nx = rs_gload(sK.x, p);
+                ny = rs_gload(sK.y, p);
+                nz = rs_gload(sK.z, p);
+                na = rs_gload(sK.amp, p);
+                nv = rs_gload(sK.vr, p);
+            }
+        };
+        fetch(pb);
 
         double2 acc[4][NJ];
 #pragma unroll
@@ -61,11 +78,12 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
             if (tid < kKP) {
                 const int64_t p = p0 + tid;
                 if (p < pe) {
-                    rs_pixel_args a = rs_pixel(J, m, tx, rx, p);
-                    sPsi[tid] = a.psi_f;
-                    sB[tid] = a.b;
-                    sBeta[tid] = a.beta;
-                    sA[tid] = (double)a.a;
+                    double psi, b, beta;
+                    rs_chan_args(sK, nx, ny, nz, nv, m, sK.tx, sK.rx, &psi, &b, &beta);
+                    sPsi[tid] = rs_frac(psi);
+                    sB[tid] = b;
+                    sBeta[tid] = beta;
+                    sA[tid] = (double)na;
                 } else {
                     sPsi[tid] = 0.0;
                     sB[tid] = 0.0;
@@ -73,6 +91,7 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
                     sA[tid] = 0.0;
                 }
             }
+            fetch(p0 + kKP);
             __syncthreads();
             {
                 // thread = (pixel q, run r of consecutive rows / columns)
@@ -100,7 +119,7 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
                 double ds, dc, ts, tc;
                 sincospi(2.0 * rs_frac(beta * (double)(l0 + DR * r)), &ds, &dc);
                 sincospi(2.0 * rs_frac(beta), &ts, &tc);
-                if (J.amp_lstride == 0) {
+                if (sK.amp_lstride == 0) {
                     dc *= a;
                     ds *= a;
 #pragma unroll
@@ -118,7 +137,7 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
                     for (int k = 0; k < DR; ++k) {
                         const int l = l0 + DR * r + k;
                         const double al =
-                            p < pe && l < J.L ? (double)J.amp[p + (int64_t)l * J.amp_lstride] : 0.0;
+                            p < pe && l < sK.L ? (double)rs_gload(sK.amp, p + (int64_t)l * sK.amp_lstride) : 0.0;
                         sD[q][DR * r + k] = make_double2(dc * al, -(ds * al));
                         const double cn = __builtin_fma(dc, tc, -(ds * ts));
                         ds = __builtin_fma(dc, ts, ds * tc);
