@@ -39,8 +39,8 @@ FLOP_PLAIN = 8         # one binary64 complex MAC
 # the kernel sources they were taken on; any change to those sources turns
 # the figure into null until the counters are taken again.
 TRAFFIC_SOURCES = ("rs_mfma.hip", "rs_device.h", "rs_internal.h")
-TRAFFIC = {"sources_sha256": "55a7259659ba39be6e282d38747633dab05e52a728a947391b510586380c2377",
-           "fetch_bytes": 10.98e6, "write_bytes": 67.35e6}
+TRAFFIC = {"sources_sha256": "61f5ee16fb6491eaee00921fe8ff606a6d097cb718dbecd5dd749c5ee4bfe7a5",
+           "fetch_bytes": 10.90e6, "write_bytes": 67.00e6}
 
 
 # Offered load of the serving leg, frozen so that latencies stay comparable
