@@ -80,6 +80,10 @@ class Oracle:
             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
         self.lib.orc_entries.restype = ctypes.c_int
+        self.lib.orc_chan_args.argtypes = [ctypes.POINTER(_Radar), ctypes.POINTER(_Pixels), ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
+        self.lib.orc_chan_args.restype = ctypes.c_int
         self.lib.orc_max_threads.argtypes = [ctypes.c_int]
         self.lib.orc_max_threads.restype = ctypes.c_int
 
@@ -148,6 +152,15 @@ class Oracle:
         if self.lib.orc_marginal_l(ctypes.byref(rs), ctypes.byref(ps), _f64p(out), threads):
             raise ValueError("oracle rejected the arguments")
         return out.view(np.complex128)[..., 0]
+
+    def chan_args(self, radar, px, c: int):
+        """(psi, b, beta) of every pixel in channel c, float64 arrays [P]."""
+        rs, keep_r = self._radar(radar)
+        ps, keep_p = self._pixels(px, radar)
+        out = [np.empty(px.P, dtype=np.float64) for _ in range(3)]
+        if self.lib.orc_chan_args(ctypes.byref(rs), ctypes.byref(ps), int(c), *[_f64p(a) for a in out]):
+            raise ValueError("oracle rejected the arguments")
+        return tuple(out)
 
     def max_threads(self, threads: int = 0) -> int:
         return int(self.lib.orc_max_threads(threads))

@@ -331,6 +331,18 @@ int orc_marginal_l(const orc_radar *r, const orc_pixels *px, double *out, int nt
     return 0;
 }
 
+/* Phase arguments of every pixel in channel c by the recipe above: psi (not
+ * reduced), b and beta, each an array of P doubles.  Serves the NUFFT
+ * oracle, which needs the arguments rather than the sum. */
+int orc_chan_args(const orc_radar *r, const orc_pixels *px, int c, double *psi, double *b, double *beta)
+{
+    if (!valid(r, px) || c < 0 || c >= r->M * r->N || (px->P > 0 && (!psi || !b || !beta))) return 1;
+    orc_consts k;
+    constants(r, &k);
+    for (int64_t p = 0; p < px->P; ++p) chan_args(r, &k, px, p, c, &psi[p], &b[p], &beta[p]);
+    return 0;
+}
+
 /* Number of OpenMP threads a parallel region would use. */
 int orc_max_threads(int nthreads)
 {
