@@ -68,7 +68,7 @@ def parse():
                     help="untimed steps first; the clock takes ~50 steps (~25 ms) of load to settle")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline single-frame measurement")
-    ap.add_argument("--legs", default="plain,variants,batch,doppler_time,serving,cpu",
+    ap.add_argument("--legs", default="plain,variants,nufft,batch,doppler_time,serving,cpu",
                     help="extra legs after the headline (comma-separated subset)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
@@ -246,6 +246,24 @@ def main():
             }
             del vcube, vdpx
             vplan.close()
+
+    if "nufft" in legs:
+        # ---- NUFFT form on the same frame (an approximation sized by a tolerance) --
+        out["nufft"] = {"workload": "the headline frame", "tolerances": {}}
+        for tol in (1e-4, 1e-6):
+            nplan = rs.rs_cube_plan_nufft(radar, rs.RS_C64, max_pixels=px.P, tolerance=tol)
+            ncube = rs.new_cube(nplan, dev)
+            nwall, nper = timed_steps(lambda: rs.rs_beat_synthesize(nplan, dpx, ncube), 50, 20)
+            torch.cuda.synchronize()
+            out["nufft"]["tolerances"][f"{tol:g}"] = {
+                "plan": json.loads(nplan.describe(px.P)),
+                "ms_per_step": nwall * 1e3 / 50, "p50_ms": pct(nper, 50), "p99_ms": pct(nper, 99),
+                "direct_sum_terms_per_s": terms / (nwall / 50),
+                "speedup_vs_mfma": (terms / (nwall / 50)) / value,
+                "parity_vs_exact": parity_sampled(radar, px, ncube.cpu().numpy(), k=256),
+            }
+            del ncube
+            nplan.close()
 
     if "batch" in legs:
         # ---- 64 animation frames in one persistent launch -------------------------

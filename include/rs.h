@@ -34,6 +34,21 @@
  *                         cores with fp32 accumulation (hi*hi + hi*lo +
  *                         lo*hi).  Typical relative L2 error vs an exact
  *                         binary64 sum: 1e-6 .. 1e-5.
+ *   RS_FORM_NUFFT         per channel a two-dimensional type-1 non-uniform
+ *                         FFT from the points (b, -beta) onto the Ns x L
+ *                         modes: binary64 phase arguments, float32
+ *                         spreading with an exponential-of-semicircle
+ *                         kernel onto a grid oversampled >= 2x, float32
+ *                         FFTs and deconvolution.  An approximation sized
+ *                         by a tolerance (rs_cube_plan_nufft; 1e-6 from
+ *                         rs_cube_plan): relative L2 error vs the exact sum
+ *                         of about the tolerance, float32 rounding
+ *                         (~1e-6) below.  Work grows with P C w^2 +
+ *                         C Ns L log, not P C Ns L.  The grid sums use
+ *                         atomics: results vary in the last bits from run
+ *                         to run.  Limits: Ns, L <= 2048, strengths
+ *                         constant over the blocks, single-frame calls
+ *                         only (batch and sessions: RS_E_UNSUPPORTED).
  *
  * Conventions
  *   - Every call returns rs_status; nothing throws or aborts across the ABI.
@@ -70,7 +85,7 @@ typedef enum {
     RS_E_NOT_FOUND = 6    /* unknown session ticket                              */
 } rs_status;
 
-typedef enum { RS_FORM_FP64_DIRECT = 0, RS_FORM_MFMA_SPLIT16 = 1 } rs_form;
+typedef enum { RS_FORM_FP64_DIRECT = 0, RS_FORM_MFMA_SPLIT16 = 1, RS_FORM_NUFFT = 2 } rs_form;
 typedef enum { RS_C64 = 0, RS_C128 = 1 } rs_dtype; /* interleaved (re, im) */
 
 /* Signal-model variants (bit flags, rs_radar.model; 0 = the model above).
@@ -142,6 +157,14 @@ typedef struct rs_session rs_session;
  * and streams at once. */
 rs_status rs_cube_plan(const rs_radar *radar, rs_form form, rs_dtype dtype,
                        int64_t max_pixels, rs_plan **out);
+
+/* A plan of the NUFFT form for a tolerance in [1e-7, 0.5): kernel width
+ * w = ceil(log10(1/tolerance)) + 1 cells (at most 8), shape beta = 2.30 w,
+ * grid the smallest power of two >= max(2 Ns, 2 w) by >= max(2 L, 2 w).
+ * Errors: as rs_cube_plan, RS_E_INVALID for a tolerance outside the range,
+ * RS_E_UNSUPPORTED for RS_MODEL_BLOCK_STRENGTH or Ns or L > 2048. */
+rs_status rs_cube_plan_nufft(const rs_radar *radar, rs_dtype dtype, int64_t max_pixels,
+                             double tolerance, rs_plan **out);
 
 /* Bytes of device workspace rs_beat_synthesize_ws needs for P pixels
  * (0 <= P <= max_pixels).  Errors: RS_E_INVALID. */

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librs.so")
 SOURCES = ["rs_api.hip", "rs_plain.hip", "rs_mfma.hip", "rs_reduce.hip", "rs_session.hip", "rs_rd.hip",
-           "rs_scene.hip"]
+           "rs_scene.hip", "rs_nufft.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

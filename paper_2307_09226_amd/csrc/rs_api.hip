@@ -219,8 +219,25 @@ rs_status rs_launch_reduce_checked(const rs_plan *pl, const rs_launch &L, hipStr
     return RS_OK;
 }
 
+static rs_status plan_common(const rs_radar *r, rs_form form, rs_dtype dtype, int64_t max_pixels, double tol,
+                             rs_plan **out);
+
 extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtype,
                                   int64_t max_pixels, rs_plan **out)
+{
+    return plan_common(r, form, dtype, max_pixels, 1e-6, out);
+}
+
+extern "C" rs_status rs_cube_plan_nufft(const rs_radar *r, rs_dtype dtype, int64_t max_pixels, double tolerance,
+                                        rs_plan **out)
+{
+    if (!(tolerance >= 1e-7 && tolerance < 0.5))
+        return rs_fail(RS_E_INVALID, "NUFFT tolerance must lie in [1e-7, 0.5)");
+    return plan_common(r, RS_FORM_NUFFT, dtype, max_pixels, tolerance, out);
+}
+
+static rs_status plan_common(const rs_radar *r, rs_form form, rs_dtype dtype, int64_t max_pixels, double tol,
+                             rs_plan **out)
 {
     if (!out) return rs_fail(RS_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -239,7 +256,7 @@ extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtyp
         if (!std::isfinite(r->tx_xyz[i])) return rs_fail(RS_E_INVALID, "non-finite Tx position");
     for (int i = 0; i < 3 * r->N; ++i)
         if (!std::isfinite(r->rx_xyz[i])) return rs_fail(RS_E_INVALID, "non-finite Rx position");
-    if (form != RS_FORM_FP64_DIRECT && form != RS_FORM_MFMA_SPLIT16)
+    if (form != RS_FORM_FP64_DIRECT && form != RS_FORM_MFMA_SPLIT16 && form != RS_FORM_NUFFT)
         return rs_fail(RS_E_INVALID, "unknown form");
     if (dtype != RS_C64 && dtype != RS_C128) return rs_fail(RS_E_INVALID, "unknown dtype");
     if (r->model < 0 || (r->model & ~(RS_MODEL_FAR_FIELD | RS_MODEL_TDM_SLOT | RS_MODEL_INTRA_CHIRP | RS_MODEL_RVP |
@@ -247,6 +264,12 @@ extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtyp
         return rs_fail(RS_E_INVALID, "unknown model flags 0x%x", (unsigned)r->model);
     if (max_pixels < 0) return rs_fail(RS_E_INVALID, "max_pixels < 0");
     if (max_pixels > ((int64_t)1 << 40)) return rs_fail(RS_E_INVALID, "max_pixels too large");
+    if (form == RS_FORM_NUFFT) {
+        if (r->model & RS_MODEL_BLOCK_STRENGTH)
+            return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form needs strengths constant over the blocks");
+        if (r->Ns > 2048 || r->L > 2048) return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves Ns, L <= 2048");
+        if ((int64_t)r->M * r->N > 65535) return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves <= 65535 channels");
+    }
 
     rs_plan *pl = new (std::nothrow) rs_plan();
     if (!pl) return rs_fail(RS_E_NOMEM, "host allocation failed");
@@ -285,6 +308,16 @@ extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtyp
     pl->dtype = dtype;
     pl->max_pixels = max_pixels;
     rs_choose_tiles(pl);
+    std::vector<float> deconv;
+    if (form == RS_FORM_NUFFT) {
+        pl->nu_tol = tol;
+        rs_nufft_params(tol, &pl->nu_w, &pl->nu_beta);
+        pl->nu_n1 = rs_nufft_fine(r->Ns, pl->nu_w);
+        pl->nu_n2 = rs_nufft_fine(r->L, pl->nu_w);
+        deconv.resize((size_t)r->Ns + r->L);
+        rs_nufft_deconv(r->Ns, pl->nu_n1, pl->nu_w, pl->nu_beta, deconv.data());
+        rs_nufft_deconv(r->L, pl->nu_n2, pl->nu_w, pl->nu_beta, deconv.data() + r->Ns);
+    }
 
     std::vector<double> ant(3 * (r->M + r->N));
     std::memcpy(ant.data(), r->tx_xyz, sizeof(double) * 3 * r->M);
@@ -298,6 +331,18 @@ extern "C" rs_status rs_cube_plan(const rs_radar *r, rs_form form, rs_dtype dtyp
         (void)hipFree(pl->d_ant);
         delete pl;
         return rs_fail(RS_E_DEVICE, "copy of the antenna table failed");
+    }
+    if (!deconv.empty()) {
+        const size_t nb = deconv.size() * sizeof(float);
+        if (hipMalloc(&pl->d_deconv, nb) != hipSuccess) {
+            pl->d_deconv = nullptr;
+            rs_plan_destroy(pl);
+            return rs_fail(RS_E_NOMEM, "hipMalloc of the NUFFT deconvolution table failed");
+        }
+        if (hipMemcpy(pl->d_deconv, deconv.data(), nb, hipMemcpyHostToDevice) != hipSuccess) {
+            rs_plan_destroy(pl);
+            return rs_fail(RS_E_DEVICE, "copy of the NUFFT deconvolution table failed");
+        }
     }
     *out = pl;
     return RS_OK;
@@ -352,9 +397,10 @@ void rs_choose_tiles(rs_plan *pl)
 extern "C" void rs_plan_destroy(rs_plan *pl)
 {
     if (!pl) return;
-    if (pl->d_ant) {
+    if (pl->d_ant || pl->d_deconv) {
         device_guard g(pl->device);
-        (void)hipFree(pl->d_ant);
+        if (pl->d_ant) (void)hipFree(pl->d_ant);
+        if (pl->d_deconv) (void)hipFree(pl->d_deconv);
     }
     delete pl;
 }
@@ -363,6 +409,10 @@ extern "C" rs_status rs_plan_workspace_bytes(const rs_plan *pl, int64_t P, size_
 {
     if (!pl || !bytes) return rs_fail(RS_E_INVALID, "NULL argument");
     if (P < 0 || P > pl->max_pixels) return rs_fail(RS_E_INVALID, "P out of range");
+    if (pl->form == RS_FORM_NUFFT) {
+        *bytes = rs_nufft_workspace(pl, P);
+        return RS_OK;
+    }
     int32_t S, chunk;
     rs_status s = rs_plan_chunking(pl, P, &S, &chunk);
     if (s != RS_OK) return s;
@@ -378,6 +428,15 @@ extern "C" rs_status rs_plan_describe(const rs_plan *pl, int64_t P, char *buf, s
     rs_status s = rs_plan_chunking(pl, P, &S, &chunk);
     if (s != RS_OK) return s;
     if (len == 0) return RS_OK;
+    if (pl->form == RS_FORM_NUFFT) {
+        snprintf(buf, len,
+                 "{\"form\": \"nufft\", \"dtype\": \"%s\", \"C\": %d, \"Ns\": %d, \"L\": %d, "
+                 "\"tolerance\": %.3g, \"kernel_width\": %d, \"kernel_beta\": %.4g, \"grid_n\": %d, "
+                 "\"grid_l\": %d, \"pixel_blocks\": %lld, \"cus\": %d, \"model\": %d}",
+                 pl->dtype == RS_C128 ? "complex128" : "complex64", pl->C, pl->Ns, pl->L, pl->nu_tol, pl->nu_w,
+                 pl->nu_beta, pl->nu_n1, pl->nu_n2, (long long)((P + 511) / 512), pl->ncu, pl->model);
+        return RS_OK;
+    }
     snprintf(buf, len,
              "{\"form\": \"%s\", \"dtype\": \"%s\", \"C\": %d, \"Ns\": %d, \"L\": %d, "
              "\"tile_n\": %d, \"tile_l\": %d, \"wave_rows\": %d, \"waves\": %d, \"n_tiles\": %d, \"l_tiles\": %d, "
@@ -400,7 +459,7 @@ extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, voi
     if (s != RS_OK) return s;
     int32_t S, chunk;
     if ((s = rs_plan_chunking(pl, px->P, &S, &chunk)) != RS_OK) return s;
-    const size_t need = rs_workspace_bytes(pl, S);
+    const size_t need = pl->form == RS_FORM_NUFFT ? rs_nufft_workspace(pl, px->P) : rs_workspace_bytes(pl, S);
     if (need > 0 && (!ws || ws_bytes < need))
         return rs_fail(RS_E_INVALID, "workspace too small: need %zu bytes", need);
     if (need > 0 && (reinterpret_cast<uintptr_t>(ws) & 255))
@@ -408,6 +467,7 @@ extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, voi
     device_guard g(pl->device);
     if (g.st != RS_OK) return g.st;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (pl->form == RS_FORM_NUFFT) return rs_nufft_enqueue(pl, px, cube, ws, st);
 
     rs_launch L;
     std::memset(&L, 0, sizeof L);
@@ -456,6 +516,8 @@ extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *fram
     if (nframes < 0) return rs_fail(RS_E_INVALID, "nframes < 0");
     if (nframes == 0) return RS_OK;
     if (!frames || !cubes) return rs_fail(RS_E_INVALID, "NULL frames or cubes");
+    if (pl->form == RS_FORM_NUFFT)
+        return rs_fail(RS_E_UNSUPPORTED, "batched frames serve the direct forms; call rs_beat_synthesize per frame");
     rs_status s;
     for (int f = 0; f < nframes; ++f)
         if ((s = rs_check_pixels(pl, &frames[f])) != RS_OK) return s;

@@ -22,6 +22,12 @@ struct rs_plan {
     int64_t items_target = 0;       // work items aimed at for one cube
     int min_chunk = 0;              // smallest pixel chunk
     int occupancy = 1;              // resident workgroups per CU of the main kernel
+    // NUFFT form
+    double nu_tol = 0;              // requested tolerance
+    int nu_w = 0;                   // kernel width (cells)
+    double nu_beta = 0;             // kernel shape
+    int nu_n1 = 0, nu_n2 = 0;       // grid size along n and l
+    float *d_deconv = nullptr;      // device: h / phi_hat for n [Ns] then for l [L]
 };
 
 rs_status rs_fail(rs_status s, const char *fmt, ...);
@@ -54,3 +60,9 @@ rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px);
 // block_strength: some job of the launch has strengths per block
 rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, bool block_strength, int grid, hipStream_t st);
 rs_status rs_launch_reduce_checked(const rs_plan *pl, const rs_launch &L, hipStream_t st);
+// NUFFT form (rs_nufft.hip)
+void rs_nufft_params(double tol, int *w, double *beta);
+int rs_nufft_fine(int N, int w);
+void rs_nufft_deconv(int N, int n, int w, double beta, float *out);
+size_t rs_nufft_workspace(const rs_plan *pl, int64_t P);
+rs_status rs_nufft_enqueue(const rs_plan *pl, const rs_pixels *px, void *cube, void *ws, hipStream_t st);

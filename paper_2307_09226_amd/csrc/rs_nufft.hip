@@ -1,0 +1,619 @@
+// NUFFT form: the cube as one two-dimensional type-1 non-uniform FFT per
+// virtual channel (gfx950).
+//
+// Per channel c the sum of Sec. II (eq. (1) per channel, pixel sum of
+// eq. (2)) is
+//   Y[c][l][n] = sum_p s_p exp(j2pi (u_p n + v_p l)),
+//   s_p = a_p exp(j2pi psi_p),  u_p = b_p,  v_p = -beta_p,
+// a type-1 NUFFT from the points (u_p, v_p) onto the Ns x L modes.  It is
+// evaluated as such a transform is (Barnett, Magland and af Klinteberg,
+// SIAM J. Sci. Comput. 41 (2019), "exponential of semicircle" kernel
+// phi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1)) of width w cells, grid
+// oversampled at least twofold):
+//   k_nufft_zero    clear the n1 x n2 grid of every channel
+//   k_nufft_spread  per (block of 512 pixels, channel): phase arguments in
+//                   binary64 (the same recipe as the direct forms), reduced
+//                   frequencies u' = u - rint(u), v' = v - rint(v), centring
+//                   phase exp(j2pi (u' floor(Ns/2) + v' floor(L/2))), and the
+//                   w x w kernel weights around (u' n1, v' n2); the points
+//                   are sorted by window column in LDS and every cell of the
+//                   block's bounding box gathers its sum in registers into
+//                   the block's tile slot (boxes of up to 1,024 cells);
+//                   larger boxes add their sums, and boxes wider than the
+//                   grid (points over all beat frequencies, or across its
+//                   periodic edge) each weight, to the grid with atomics
+//   k_nufft_assemble  the tile slots added to the grid: four threads per cell
+//                   sum, in block order, a quarter each of the tiles whose box
+//                   covers it, and the quarters are added in a fixed order (no
+//                   atomics on the cells every block touches)
+//   k_nufft_rows    FFT (+ sign) of every grid row of length n1 in LDS; the
+//                   Ns kept modes times the deconvolution factor h / phi_hat
+//                   go to a row buffer [C][n2][Ns]
+//   k_nufft_cols    FFT (+ sign) of every column of length n2, the L kept
+//                   modes times their deconvolution factor into the cube
+// Arithmetic: phase arguments binary64; strengths, weights, grid and FFTs
+// float32.  The sums are formed in a fixed order when every box fits a tile
+// slot; boxes that do not are added with atomics, and then the order of the
+// additions, and the last bits of the result, vary from run to run.
+#include "rs_api_internal.h"
+#include "rs_device.h"
+#include "rs_fft.h"
+
+#include <climits>
+#include <cmath>
+#include <vector>
+
+namespace {
+
+constexpr int kSpreadThreads = 256;
+constexpr int kBlockPts = 512;                        // pixels per spreading workgroup (power of two)
+constexpr int kMaxCols = 2048;                        // widest box gathered per cell
+constexpr int kSlot = 1024;                           // tile cells kept per (block, channel)
+constexpr int kMaskBlocks = 1024;                     // blocks per coverage pass of a row
+constexpr int kSplit = 4;                             // threads per cell in the assembly
+constexpr int kAsmCols = 256 / kSplit;                // grid columns per assembly workgroup
+constexpr int kFftThreads = 256;
+constexpr int kFftElems = 4096;                       // complex values per FFT workgroup
+
+struct nu_args {
+    const float *x, *y, *z, *amp, *vr;
+    int64_t P;
+    const double *ant;          // tx[M][3] then rx[N][3]
+    double Kc, Kb, Kd, Kf, Krvp;
+    int32_t M, N, Ns, L, model;
+    int32_t n1, n2;             // grid size along n and l (powers of two)
+    float beta;                 // kernel shape
+    float2 *grid;               // [C][n2][n1]: weights of boxes that do not fit a tile slot
+    float2 *rows;               // [C][n2][Ns]
+    float2 *tiles;              // [C][nblk][kSlot]: each block's box sums, row-major e1 x e2
+    int4 *desc;                 // [C][nblk]: box (lo1, lo2, e1, e2); e1 = 0 when not in a slot
+    int *rowcov;                // [C][n2]: nonzero when some slot covers the grid row
+    int32_t nblk;               // pixel blocks
+    const float *d1, *d2;       // deconvolution factors [Ns], [L]
+    void *cube;                 // [C][L][Ns]
+};
+
+__device__ __forceinline__ void gatomic_add(float *p, float v)
+{
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) float *)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int pmod(int a, int n) { return ((a % n) + n) % n; }
+
+// Kernel weight at offset t (cells) from the point; zero outside |t| <= w/2.
+template <int W>
+__device__ __forceinline__ float es_weight(float t, float beta)
+{
+    const float z = t * (2.0f / W);
+    const float q = 1.0f - z * z;
+    return q > 0.0f ? expf(beta * (__builtin_sqrtf(q) - 1.0f)) : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_nufft_zero(float4 *p, int64_t n4)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Block-wide minimum (is_min) or maximum of v; every thread gets it.
+__device__ __forceinline__ int block_reduce(int v, int *red, bool is_min)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int w = __shfl_xor(v, o);
+        v = is_min ? min(v, w) : max(v, w);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = red[0];
+    for (int i = 1; i < kSpreadThreads / 64; ++i) r = is_min ? min(r, red[i]) : max(r, red[i]);
+    __syncthreads();
+    return r;
+}
+
+// Spreading of one pixel block onto one channel's grid, gathered per cell.
+//   1. A thread per pixel evaluates its point into LDS: the first cells
+//      (m1, m2) of its W x W window, its strength c and the 2 W kernel
+//      weights; the block's bounding box of cells follows by reduction.
+//   2. The points are sorted by window column (bitonic sort of
+//      (m1 - lo1, index) keys, so the order is fixed), and cs[k] marks where
+//      column k starts.
+//   3. A thread per box cell (x, y) sums, in registers, c w1[x - m1]
+//      w2[y - m2] over the points whose window covers it -- those with
+//      m1 - lo1 in [x - W + 1, x], a contiguous run of the sorted order --
+//      and adds the sum to the grid cell with one global atomic per part.
+// No LDS atomics: neighbouring pixels share most of their window, and
+// atomics on the same LDS cells from successive instructions serialise.
+template <int W>
+__global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
+{
+    __shared__ int pm1[kBlockPts], pm2[kBlockPts];
+    __shared__ float2 pc[kBlockPts];
+    __shared__ float pw1[kBlockPts * W], pw2[kBlockPts * W];
+    __shared__ int key[kBlockPts];
+    __shared__ int cs[kMaxCols + 1];
+    __shared__ int4 srec[kBlockPts];      // sorted: (m1 - lo1, m2 - lo2, point index, 0)
+    __shared__ float2 spc[kBlockPts];     // sorted strengths
+    __shared__ int red[kSpreadThreads / 64];
+    const int tid = threadIdx.x;
+    const int c = blockIdx.y;
+    const int m = c / A.N, r = c % A.N;
+    double tx[3], rx[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        tx[i] = rs_gload(A.ant, 3 * m + i);
+        rx[i] = rs_gload(A.ant, 3 * (A.M + r) + i);
+    }
+    const int64_t p0 = (int64_t)blockIdx.x * kBlockPts;
+    const int npts = (int)min<int64_t>(kBlockPts, A.P - p0);
+    int lo1 = INT_MAX, hi1 = INT_MIN, lo2 = INT_MAX, hi2 = INT_MIN;
+    for (int q = tid; q < npts; q += kSpreadThreads) {
+        const int64_t p = p0 + q;
+        double psi, b, beta;
+        rs_chan_args(A, rs_gload(A.x, p), rs_gload(A.y, p), rs_gload(A.z, p), rs_gload(A.vr, p), m, tx, rx, &psi,
+                     &b, &beta);
+        const double u = b - __builtin_rint(b);
+        const double v = -beta - __builtin_rint(-beta);
+        double th = rs_frac(psi) + u * (double)(A.Ns / 2) + v * (double)(A.L / 2);
+        th = rs_frac(th);
+        float sn, cs_;
+        sincospif(2.0f * (float)th, &sn, &cs_);
+        const float a = rs_gload(A.amp, p);
+        pc[q] = make_float2(a * cs_, a * sn);
+        // first cell of the W-cell window and the weights at its cells; the
+        // offset from the point is formed in binary64 so that the weights see
+        // it to float32 precision whatever the grid size
+        const double t1 = u * (double)A.n1, t2 = v * (double)A.n2;
+        const double s1 = __builtin_ceil(t1 - 0.5 * W), s2 = __builtin_ceil(t2 - 0.5 * W);
+        const int c1 = (int)s1, c2 = (int)s2;
+        pm1[q] = c1;
+        pm2[q] = c2;
+        const float o1 = (float)(s1 - t1), o2 = (float)(s2 - t2);
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            pw1[q * W + i] = es_weight<W>(o1 + (float)i, A.beta);
+            pw2[q * W + i] = es_weight<W>(o2 + (float)i, A.beta);
+        }
+        lo1 = min(lo1, c1);
+        hi1 = max(hi1, c1);
+        lo2 = min(lo2, c2);
+        hi2 = max(hi2, c2);
+    }
+    lo1 = block_reduce(lo1, red, true);   // the barriers also publish the points
+    if (lo1 == INT_MAX) return;           // no pixel in this block (uniform)
+    hi1 = block_reduce(hi1, red, false);
+    lo2 = block_reduce(lo2, red, true);
+    hi2 = block_reduce(hi2, red, false);
+    const int e1 = hi1 - lo1 + W, e2 = hi2 - lo2 + W;   // box of cells touched
+    float2 *grid = A.grid + (int64_t)c * A.n2 * A.n1;
+
+    int4 *dsc = A.desc + (int64_t)c * A.nblk + blockIdx.x;
+    const bool slot = e1 * e2 <= kSlot && hi1 - lo1 < kMaxCols && e1 <= A.n1 && e2 <= A.n2;
+    if (tid == 0) *dsc = make_int4(lo1, lo2, slot ? e1 : 0, e2);
+    if (slot && tid < e2) atomicOr(A.rowcov + (int64_t)c * A.n2 + pmod(lo2 + tid, A.n2), 1);
+    if (hi1 - lo1 >= kMaxCols || e1 > A.n1 || e2 > A.n2) {
+        // box wider than the grid or the column table: scatter each weight
+        // to the grid (a lane per window cell, a wave per point)
+        const int lane = tid & 63, wave = tid >> 6;
+        const int i = lane % W, j = lane / W;
+        if (lane < W * W) {
+            for (int q = wave; q < npts; q += kSpreadThreads / 64) {
+                const float w = pw1[q * W + i] * pw2[q * W + j];
+                const float2 cv = pc[q];
+                float2 *cell = grid + (int64_t)pmod(pm2[q] + j, A.n2) * A.n1 + pmod(pm1[q] + i, A.n1);
+                gatomic_add(&cell->x, cv.x * w);
+                gatomic_add(&cell->y, cv.y * w);
+            }
+        }
+        return;
+    }
+
+    // ---- 2. sort by window column: key = (m1 - lo1) * kBlockPts + q --------
+    for (int q = tid; q < kBlockPts; q += kSpreadThreads)
+        key[q] = q < npts ? (pm1[q] - lo1) * kBlockPts + q : INT_MAX;
+    __syncthreads();
+    for (int k = 2; k <= kBlockPts; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = tid; t < kBlockPts / 2; t += kSpreadThreads) {
+                const int i0 = 2 * t - (t & (jj - 1));
+                const int i1 = i0 + jj;
+                const int a = key[i0], bb = key[i1];
+                const bool up = (i0 & k) == 0;
+                if ((a > bb) == up) {
+                    key[i0] = bb;
+                    key[i1] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // cs[k] = first sorted position whose column is >= k, k = 0 .. ncol;
+    // the records are copied into sorted order so that the gather reads them
+    // without an indirection
+    const int ncol = hi1 - lo1 + 1;
+    for (int s = tid; s < npts; s += kSpreadThreads) {
+        const int q = key[s] % kBlockPts;
+        srec[s] = make_int4(pm1[q] - lo1, pm2[q] - lo2, q, 0);
+        spc[s] = pc[q];
+        const int col = key[s] / kBlockPts;
+        const int prev = s == 0 ? -1 : key[s - 1] / kBlockPts;
+        for (int k = prev + 1; k <= col; ++k) cs[k] = s;
+        if (s == npts - 1)
+            for (int k = col + 1; k <= ncol; ++k) cs[k] = npts;
+    }
+    __syncthreads();
+
+    // ---- 3. gather per cell, one atomic pair per nonzero cell ---------------
+    for (int cell = tid; cell < e1 * e2; cell += kSpreadThreads) {
+        const int y = cell / e1, x = cell - y * e1;
+        const int k0 = max(0, x - W + 1), k1 = min(x, ncol - 1);
+        const int sb = cs[k0], se = cs[k1 + 1];
+        float sr = 0.f, si = 0.f;
+        // kU candidates per round, their reads issued together; the points
+        // of this column range have dx in [0, W) by construction
+        constexpr int kU = 8;
+        for (int s0 = sb; s0 < se; s0 += kU) {
+            int4 rec[kU];
+            float2 cv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int si_ = min(s0 + u, se - 1);
+                rec[u] = srec[si_];
+                cv[u] = spc[si_];
+            }
+            float w1v[kU], w2v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int dx = x - rec[u].x, dy = y - rec[u].y;
+                const bool hit = s0 + u < se && dy >= 0 && dy < W;
+                const int base = rec[u].z * W;
+                w1v[u] = pw1[base + (hit ? dx : 0)];
+                w2v[u] = hit ? pw2[base + dy] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const float w = w1v[u] * w2v[u];
+                sr = __builtin_fmaf(cv[u].x, w, sr);
+                si = __builtin_fmaf(cv[u].y, w, si);
+            }
+        }
+        if (slot) {
+            // the row-FFT kernel adds the slot to the grid rows it covers
+            A.tiles[((int64_t)c * A.nblk + blockIdx.x) * kSlot + cell] = make_float2(sr, si);
+        } else if (sr != 0.f || si != 0.f) {
+            float2 *g = grid + (int64_t)pmod(lo2 + y, A.n2) * A.n1 + pmod(lo1 + x, A.n1);
+            gatomic_add(&g->x, sr);
+            gatomic_add(&g->y, si);
+        }
+    }
+}
+
+// Adds the tile slots to the grid: a workgroup per (channel, grid row, 64
+// columns), four threads per cell.  The blocks whose box covers the row are
+// listed in LDS in block order (a coverage bitmask, set in any order, read in
+// order), and every cell sums its tiles in that order, so the result does
+// not depend on scheduling.  Rows no slot covers (their flag, set by the
+// spreading kernel, is zero) return at once.
+__global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
+{
+    constexpr int kWords = kMaskBlocks / 32;
+    __shared__ unsigned mask[kWords];
+    __shared__ int woff[kWords];
+    __shared__ int4 ldesc[kMaskBlocks];   // descriptors of the covering blocks, in block order
+    __shared__ int lid[kMaskBlocks];
+    __shared__ int ncov;
+    __shared__ float2 part[kSplit][kAsmCols];
+    const int c = blockIdx.z, m2 = blockIdx.y;
+    if (rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) == 0) return;   // no slot covers this row
+    // thread = (column, quarter of the covering list): the four partial sums
+    // of a cell are added in a fixed order at the end
+    const int lc = threadIdx.x % kAsmCols, sp = threadIdx.x / kAsmCols;
+    const int col = blockIdx.x * kAsmCols + lc;
+    const int4 *dc = A.desc + (int64_t)c * A.nblk;
+    const float2 *tc = A.tiles + (int64_t)c * A.nblk * kSlot;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b0 = 0; b0 < A.nblk; b0 += kMaskBlocks) {
+        const int nb = min(kMaskBlocks, A.nblk - b0);
+        const int nw = (nb + 31) / 32;
+        for (int w = threadIdx.x; w < nw; w += blockDim.x) mask[w] = 0u;
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            const int4 d = dc[b0 + b];
+            if (d.z > 0 && pmod(m2 - d.y, A.n2) < d.w) atomicOr(&mask[b >> 5], 1u << (b & 31));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int o = 0;
+            for (int w = 0; w < nw; ++w) {
+                woff[w] = o;
+                o += __builtin_popcount(mask[w]);
+            }
+            ncov = o;
+        }
+        __syncthreads();
+        const int nc = ncov;
+        if (nc > 0) {
+            for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+                unsigned bits = mask[w];
+                int o = woff[w];
+                while (bits) {
+                    const int b = b0 + w * 32 + __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    lid[o] = b;
+                    ldesc[o] = dc[b];
+                    ++o;
+                }
+            }
+            __syncthreads();
+            if (col < A.n1) {
+                const int kb = (int)((int64_t)nc * sp / kSplit), ke = (int)((int64_t)nc * (sp + 1) / kSplit);
+                // kU covering blocks per round: their tile loads are in flight together
+                constexpr int kU = 8;
+                for (int k0 = kb; k0 < ke; k0 += kU) {
+                    float2 t[kU];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        t[u] = make_float2(0.f, 0.f);
+                        if (k0 + u < ke) {
+                            const int4 d = ldesc[k0 + u];
+                            const int xx = pmod(col - d.x, A.n1);
+                            if (xx < d.z)
+                                t[u] = rs_gload2(tc + (int64_t)lid[k0 + u] * kSlot, pmod(m2 - d.y, A.n2) * d.z + xx);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kU; ++u) {
+                        acc.x += t[u].x;
+                        acc.y += t[u].y;
+                    }
+                }
+            }
+        }
+        __syncthreads();   // mask and list are rebuilt for the next block range
+    }
+    part[sp][lc] = acc;
+    __syncthreads();
+    if (sp == 0 && col < A.n1) {
+        float2 *g = A.grid + ((int64_t)c * A.n2 + m2) * A.n1 + col;
+        float2 v = rs_gload2(g, 0);
+#pragma unroll
+        for (int k = 0; k < kSplit; ++k) {
+            v.x += part[k][lc].x;
+            v.y += part[k][lc].y;
+        }
+        *g = v;
+    }
+}
+
+// FFT (+ sign) of `rows` grid rows of length n1 per workgroup; the Ns kept
+// modes k = n - floor(Ns/2) (index k mod n1) times d1[n] into the row buffer.
+__global__ __launch_bounds__(kFftThreads) void k_nufft_rows(nu_args A, int logn1, int rpw, int64_t rows_total)
+{
+    extern __shared__ float2 smem[];
+    const int n1 = 1 << logn1;
+    float2 *tw = smem;
+    float2 *x = smem + n1 / 2;
+    const int64_t r0 = (int64_t)blockIdx.x * rpw;
+    const int rows = (int)min<int64_t>(rpw, rows_total - r0);
+    if (rows <= 0) return;
+    twiddles(tw, n1, +1.0);
+    const float2 *src = A.grid + r0 * n1;
+    for (int e = threadIdx.x; e < rows * n1; e += blockDim.x) {
+        const int row = e >> logn1, col = e & (n1 - 1);
+        x[row * n1 + bitrev(col, logn1)] = rs_gload2(src, e);
+    }
+    __syncthreads();
+    fft_rows(x, rows, logn1, tw);
+    const int h = A.Ns / 2;
+    float2 *dst = A.rows + r0 * A.Ns;
+    for (int e = threadIdx.x; e < rows * A.Ns; e += blockDim.x) {
+        const int row = e / A.Ns, n = e - row * A.Ns;
+        const int k = n - h;
+        const float2 v = x[row * n1 + (k < 0 ? k + n1 : k)];
+        const float d = rs_gload(A.d1, n);
+        dst[e] = make_float2(v.x * d, v.y * d);
+    }
+}
+
+// FFT (+ sign) along l of kb columns n0 .. n0 + kb - 1 of one channel's row
+// buffer; the L kept modes k = l - floor(L/2) times d2[l] into the cube.
+template <typename OT>
+__global__ __launch_bounds__(kFftThreads) void k_nufft_cols(nu_args A, int logn2, int kb, int groups)
+{
+    extern __shared__ float2 smem[];
+    const int n2 = 1 << logn2;
+    float2 *tw = smem;
+    float2 *x = smem + n2 / 2;  // [kb][n2]
+    const int c = blockIdx.x / groups;
+    const int n0 = (blockIdx.x % groups) * kb;
+    const int kn = min(kb, A.Ns - n0);
+    twiddles(tw, n2, +1.0);
+    const float2 *src = A.rows + (int64_t)c * n2 * A.Ns + n0;
+    for (int e = threadIdx.x; e < n2 * kb; e += blockDim.x) {
+        const int m2 = e / kb, kk = e - m2 * kb;
+        x[kk * n2 + bitrev(m2, logn2)] = kk < kn ? rs_gload2(src, (int64_t)m2 * A.Ns + kk) : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_rows(x, kb, logn2, tw);
+    const int h = A.L / 2;
+    OT *out = reinterpret_cast<OT *>(A.cube) + (int64_t)c * A.L * A.Ns + n0;
+    for (int e = threadIdx.x; e < A.L * kb; e += blockDim.x) {
+        const int l = e / kb, kk = e - l * kb;
+        if (kk >= kn) continue;
+        const int k = l - h;
+        const float2 v = x[kk * n2 + (k < 0 ? k + n2 : k)];
+        const float d = rs_gload(A.d2, l);
+        OT o;
+        o.x = v.x * d;
+        o.y = v.y * d;
+        out[(int64_t)l * A.Ns + kk] = o;
+    }
+}
+
+template <int W>
+void launch_spread(const nu_args &A, int C, hipStream_t st)
+{
+    const dim3 grid((unsigned)((A.P + kBlockPts - 1) / kBlockPts), (unsigned)C);
+    hipLaunchKernelGGL(k_nufft_spread<W>, grid, dim3(kSpreadThreads), 0, st, A);
+}
+
+int log2i(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton's method on the
+// Legendre polynomial from the Chebyshev-like first guesses).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+// Kernel parameters for a tolerance (twofold oversampling): width
+// w = ceil(log10(1/tol)) + 1 cells (2 .. 8 for the tolerances a plan
+// accepts), shape beta = 2.30 w (2.20 w, 2.26 w, 2.38 w for w = 2, 3, 4).
+void rs_nufft_params(double tol, int *w, double *beta)
+{
+    int ww = (int)std::ceil(std::log10(1.0 / tol)) + 1;
+    ww = ww < 2 ? 2 : (ww > 8 ? 8 : ww);
+    const double per = ww == 2 ? 2.20 : ww == 3 ? 2.26 : ww == 4 ? 2.38 : 2.30;
+    *w = ww;
+    *beta = per * ww;
+}
+
+int rs_nufft_fine(int N, int w)
+{
+    int n = 1;
+    while (n < 2 * N || n < 2 * w) n *= 2;
+    return n;
+}
+
+// h / phi_hat(k) for the centred modes k = i - floor(N/2), i < N, on an
+// n-point grid: phi_hat(k) = integral of phi(x) cos(k x) over radians x,
+// by 200-node Gauss-Legendre quadrature in binary64.
+void rs_nufft_deconv(int N, int n, int w, double beta, float *out)
+{
+    std::vector<double> z, q;
+    gauss_legendre(200, z, q);
+    const double h = 2.0 * M_PI / n, half = 0.5 * w * h;
+    for (int i = 0; i < N; ++i) {
+        const double k = (double)(i - N / 2);
+        double s = 0.0;
+        for (size_t j = 0; j < z.size(); ++j)
+            s += q[j] * std::exp(beta * (std::sqrt(1.0 - z[j] * z[j]) - 1.0)) * std::cos(k * half * z[j]);
+        out[i] = (float)(h / (half * s));
+    }
+}
+
+// Workspace: grid, row buffer, tile slots and box descriptors.
+size_t rs_nufft_workspace(const rs_plan *pl, int64_t P)
+{
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t nblk = (P + kBlockPts - 1) / kBlockPts;
+    return up((size_t)pl->C * pl->nu_n1 * pl->nu_n2 * 8) + up((size_t)pl->C * pl->nu_n2 * 4) +
+           up((size_t)pl->C * pl->nu_n2 * pl->Ns * 8) + up((size_t)pl->C * nblk * kSlot * 8) +
+           up((size_t)pl->C * nblk * sizeof(int4));
+}
+
+rs_status rs_nufft_enqueue(const rs_plan *pl, const rs_pixels *px, void *cube, void *ws, hipStream_t st)
+{
+    nu_args A;
+    A.x = px->x;
+    A.y = px->y;
+    A.z = px->z;
+    A.amp = px->amp;
+    A.vr = px->vr;
+    A.P = px->P;
+    A.ant = pl->d_ant;
+    A.Kc = pl->Kc;
+    A.Kb = pl->Kb;
+    A.Kd = pl->Kd;
+    A.Kf = pl->Kf;
+    A.Krvp = pl->Krvp;
+    A.M = pl->M;
+    A.N = pl->N;
+    A.Ns = pl->Ns;
+    A.L = pl->L;
+    A.model = pl->model;
+    A.n1 = pl->nu_n1;
+    A.n2 = pl->nu_n2;
+    A.beta = (float)pl->nu_beta;
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    A.nblk = (int32_t)((px->P + kBlockPts - 1) / kBlockPts);
+    char *w = static_cast<char *>(ws);
+    A.grid = reinterpret_cast<float2 *>(w);
+    w += up((size_t)pl->C * pl->nu_n1 * pl->nu_n2 * 8);
+    A.rowcov = reinterpret_cast<int *>(w);
+    w += up((size_t)pl->C * pl->nu_n2 * 4);
+    const size_t zero_bytes = (size_t)(w - static_cast<char *>(ws));   // grid and row flags
+    A.rows = reinterpret_cast<float2 *>(w);
+    w += up((size_t)pl->C * pl->nu_n2 * pl->Ns * 8);
+    A.tiles = reinterpret_cast<float2 *>(w);
+    w += up((size_t)pl->C * A.nblk * kSlot * 8);
+    A.desc = reinterpret_cast<int4 *>(w);
+    A.d1 = pl->d_deconv;
+    A.d2 = pl->d_deconv + pl->Ns;
+    A.cube = cube;
+
+    const int64_t n4 = (int64_t)(zero_bytes / 16);
+    const int zgrid = (int)std::min<int64_t>((n4 + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_nufft_zero, dim3(zgrid), dim3(256), 0, st, reinterpret_cast<float4 *>(A.grid), n4);
+    if (A.P > 0) {
+        switch (pl->nu_w) {
+        case 2: launch_spread<2>(A, pl->C, st); break;
+        case 3: launch_spread<3>(A, pl->C, st); break;
+        case 4: launch_spread<4>(A, pl->C, st); break;
+        case 5: launch_spread<5>(A, pl->C, st); break;
+        case 6: launch_spread<6>(A, pl->C, st); break;
+        case 7: launch_spread<7>(A, pl->C, st); break;
+        case 8: launch_spread<8>(A, pl->C, st); break;
+        default: return rs_fail(RS_E_UNSUPPORTED, "NUFFT kernel width %d not built", pl->nu_w);
+        }
+    }
+    if (A.nblk > 0)
+        hipLaunchKernelGGL(k_nufft_assemble, dim3((unsigned)((pl->nu_n1 + kAsmCols - 1) / kAsmCols),
+                                                  (unsigned)pl->nu_n2, (unsigned)pl->C),
+                           dim3(kFftThreads), 0, st, A);
+    const int logn1 = log2i(pl->nu_n1), logn2 = log2i(pl->nu_n2);
+    const int rpw = std::max(1, kFftElems / pl->nu_n1);
+    const int64_t rows_total = (int64_t)pl->C * pl->nu_n2;
+    const size_t lds1 = (size_t)(pl->nu_n1 / 2 + rpw * pl->nu_n1) * sizeof(float2);
+    hipLaunchKernelGGL(k_nufft_rows, dim3((unsigned)((rows_total + rpw - 1) / rpw)), dim3(kFftThreads), lds1, st, A,
+                       logn1, rpw, rows_total);
+    const int kb = std::max(1, std::min(16, kFftElems / pl->nu_n2));
+    const int groups = (pl->Ns + kb - 1) / kb;
+    const size_t lds2 = (size_t)(pl->nu_n2 / 2 + kb * pl->nu_n2) * sizeof(float2);
+    if (pl->dtype == RS_C128)
+        hipLaunchKernelGGL(k_nufft_cols<double2>, dim3((unsigned)(pl->C * groups)), dim3(kFftThreads), lds2, st, A,
+                           logn2, kb, groups);
+    else
+        hipLaunchKernelGGL(k_nufft_cols<float2>, dim3((unsigned)(pl->C * groups)), dim3(kFftThreads), lds2, st, A,
+                           logn2, kb, groups);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "NUFFT launch: %s", hipGetErrorString(e));
+    return RS_OK;
+}

@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RS_LIBRARY") or os.path.join(_PKG, "librs.so")
 
 RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_UNSUPPORTED, RS_E_BUSY, RS_E_NOT_FOUND = range(7)
-RS_FORM_FP64_DIRECT, RS_FORM_MFMA_SPLIT16 = 0, 1
+RS_FORM_FP64_DIRECT, RS_FORM_MFMA_SPLIT16, RS_FORM_NUFFT = 0, 1, 2
 RS_C64, RS_C128 = 0, 1
 RS_REQ_QUEUED, RS_REQ_RUNNING, RS_REQ_DONE, RS_REQ_FAILED, RS_REQ_CANCELLED = range(5)
 RS_MODEL_FAR_FIELD, RS_MODEL_TDM_SLOT, RS_MODEL_INTRA_CHIRP, RS_MODEL_RVP, RS_MODEL_BLOCK_STRENGTH = 1, 2, 4, 8, 16
@@ -90,6 +90,8 @@ _VP = ctypes.c_void_p
 SIGNATURES = {
     "rs_cube_plan": (ctypes.c_int, [ctypes.POINTER(rs_radar), ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int64, ctypes.POINTER(_VP)]),
+    "rs_cube_plan_nufft": (ctypes.c_int, [ctypes.POINTER(rs_radar), ctypes.c_int, ctypes.c_int64,
+                                          ctypes.c_double, ctypes.POINTER(_VP)]),
     "rs_plan_workspace_bytes": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "rs_plan_describe": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_char_p, ctypes.c_size_t]),
     "rs_beat_synthesize": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP]),
@@ -259,6 +261,14 @@ def rs_cube_plan(radar, form: int = RS_FORM_MFMA_SPLIT16, dtype: int = RS_C64,
     h = ctypes.c_void_p()
     _check(lib.rs_cube_plan(ctypes.byref(st), form, dtype, max_pixels, ctypes.byref(h)))
     return Plan(h.value, radar, form, dtype, max_pixels)
+
+
+def rs_cube_plan_nufft(radar, dtype: int = RS_C64, max_pixels: int = 1 << 20,
+                       tolerance: float = 1e-6) -> Plan:
+    st, keep = _radar_struct(radar)
+    h = ctypes.c_void_p()
+    _check(lib.rs_cube_plan_nufft(ctypes.byref(st), dtype, max_pixels, float(tolerance), ctypes.byref(h)))
+    return Plan(h.value, radar, RS_FORM_NUFFT, dtype, max_pixels)
 
 
 def new_cube(plan: Plan, device="cuda:0", count: Optional[int] = None):

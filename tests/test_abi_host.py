@@ -80,3 +80,21 @@ def test_invalid_plan_arguments_rejected_on_host():
     assert rs.lib.rs_plan_workspace_bytes(None, 0, ctypes.byref(out)) == rs.RS_E_INVALID
     rs.lib.rs_plan_destroy(None)
     rs.lib.rs_session_destroy(None)
+
+
+def test_nufft_plan_arguments_rejected_on_host():
+    """The NUFFT form's tolerance range and limits are checked before any
+    device call."""
+    import dataclasses
+    from paper_2307_09226_amd import rs, scenes
+    r = scenes.radar_small()
+    st, keep = rs._radar_struct(r)
+    h = ctypes.c_void_p()
+    for tol in (0.0, 1e-8, 0.5, 2.0, float("nan"), -1e-3):
+        assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st), 0, 10, tol, ctypes.byref(h)) == rs.RS_E_INVALID, tol
+        assert h.value is None
+    for kw, code in ((dict(model=16), rs.RS_E_UNSUPPORTED), (dict(Ns=4096), rs.RS_E_UNSUPPORTED),
+                     (dict(L=4096), rs.RS_E_UNSUPPORTED), (dict(model=64), rs.RS_E_INVALID)):
+        st2, keep2 = rs._radar_struct(dataclasses.replace(r, **kw))
+        assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st2), 0, 10, 1e-6, ctypes.byref(h)) == code, kw
+        assert rs.lib.rs_cube_plan(ctypes.byref(st2), rs.RS_FORM_NUFFT, 0, 10, ctypes.byref(h)) == code, kw

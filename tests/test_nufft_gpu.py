@@ -1,0 +1,143 @@
+"""NUFFT form on the GPU: against the NUFFT oracle (same kernel, grid and
+modes; differences are float32 rounding) and against the exact direct sum
+(differences are the tolerance plus that rounding).
+
+Gates.  The float32 path rounds each strength and weight (2^-24 relative),
+sums up to a few hundred weighted points per grid cell and runs two float32
+FFTs of log2(n) <= 12 radix-2 stages; with errors adding in quadrature that
+is a few 1e-7 relative L2, so 2e-6 against the NUFFT oracle leaves a
+margin of several times.  Against the exact sum the gate is the tolerance
+plus that float32 term."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import nufft as onufft
+from paper_2307_09226_amd import scenes
+from gpu_util import errors, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+GATE_FP32 = 2e-6
+
+
+def _rs():
+    from paper_2307_09226_amd import rs
+    return rs
+
+
+def _synth(r, px, tol, dtype=0, ws=False):
+    import torch
+    rs = _rs()
+    plan = rs.rs_cube_plan_nufft(r, dtype, max_pixels=max(px.P, 1), tolerance=tol)
+    cube = rs.new_cube(plan)
+    dpx = rs.DevicePixels.from_host(px)
+    if ws:
+        buf = torch.empty(max(plan.workspace_bytes(px.P), 1), dtype=torch.uint8, device="cuda:0")
+        rs.rs_beat_synthesize_ws(plan, dpx, cube, buf)
+    else:
+        rs.rs_beat_synthesize(plan, dpx, cube)
+    torch.cuda.synchronize()
+    out = cube.cpu().numpy()
+    plan.close()
+    return out
+
+
+RADARS = {
+    "odd": lambda: scenes.radar_for(2, 3, 37, 11, Fs=10e6, Tb=120e-6),
+    "ragged": lambda: scenes.radar_for(3, 2, 72, 40, Fs=10e6, Tb=120e-6),
+    "frame_shape": lambda: scenes.radar_for(3, 4, 256, 128, Fs=10e6, Tb=120e-6),
+}
+
+
+@pytest.mark.parametrize("name", list(RADARS))
+@pytest.mark.parametrize("tol", [1e-2, 1e-4, 1e-6])
+def test_against_nufft_oracle_and_exact(name, tol):
+    r = RADARS[name]()
+    px = scenes.tiny_scene(400 + len(name), 2500, vmax=6.0)
+    got = _synth(r, px, tol)
+    ref_nu = onufft.nufft_cube(r, px, tol)
+    ref = oracle.cube(r, px)
+    rel_nu, _ = errors(got, ref_nu)
+    rel, mx = errors(got, ref)
+    print(f"nufft {name} tol={tol:g}: vs NUFFT oracle {rel_nu:.2e}, vs exact {rel:.2e} (max {mx:.2e})",
+          flush=True)
+    assert rel_nu <= GATE_FP32
+    assert rel <= tol + GATE_FP32
+
+
+@pytest.mark.parametrize("model", [15, 1, 2 | 4 | 8])
+def test_variants_and_complex128(model):
+    r = dataclasses.replace(RADARS["ragged"](), model=model)
+    px = scenes.tiny_scene(420 + model, 1500, vmax=6.0)
+    got = _synth(r, px, 1e-5, dtype=1, ws=True)
+    assert got.dtype == np.complex128
+    rel, _ = errors(got, oracle.cube(r, px))
+    rel_nu, _ = errors(got, onufft.nufft_cube(r, px, 1e-5))
+    print(f"nufft model={model}: vs exact {rel:.2e}, vs NUFFT oracle {rel_nu:.2e}", flush=True)
+    assert rel_nu <= GATE_FP32 and rel <= 1e-5 + GATE_FP32
+
+
+def test_points_across_the_grid_and_its_edge():
+    """Points spread over every frequency, several beyond Nyquist (wrapped):
+    the bounding boxes exceed the LDS tile and the weights go straight to the
+    grid; beat frequencies at +-1/2 cycle straddle its periodic edge."""
+    rng = np.random.default_rng(430)
+    r = RADARS["ragged"]()
+    P = 5000
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    Kb = 2 * r.mu / (r.c0 * r.Fs)
+    rr = rng.uniform(0.3, 1.2 / Kb, P)           # beat frequencies 0 .. 1.2 cycles
+    az = rng.uniform(-1.0, 1.0, P)
+    px = scenes.Pixels(f32(rr * np.sin(az)), f32(rr * np.cos(az)), f32(rng.uniform(-1, 1, P)),
+                       f32(rng.lognormal(0, 0.5, P)), f32(rng.uniform(-9, 9, P)))
+    got = _synth(r, px, 1e-6)
+    rel_nu, _ = errors(got, onufft.nufft_cube(r, px, 1e-6))
+    rel, _ = errors(got, oracle.cube(r, px))
+    print(f"nufft spread-out points: vs NUFFT oracle {rel_nu:.2e}, vs exact {rel:.2e}", flush=True)
+    assert rel_nu <= GATE_FP32 and rel <= 1e-6 + GATE_FP32
+
+
+def test_frame_sampled():
+    """The 65,536-pixel frame (3 x 4, Ns 256, L 128) at tolerance 1e-6:
+    sampled entries against the exact sum."""
+    radar, px = scenes.workload_frame()
+    got = _synth(radar, px, 1e-6)
+    c, l, n = sample_indices(radar.cube_shape(), 300, seed=12)
+    rel, mx = errors(got[c, l, n], oracle.entries(radar, px, c, l, n))
+    print(f"nufft frame: relL2 {rel:.2e} maxabs {mx:.2e}", flush=True)
+    assert rel <= 1e-6 + GATE_FP32
+
+
+def test_edge_sizes_and_refusals():
+    """P = 0 gives an exact zero cube; one pixel and a pixel count that
+    leaves a partial block match the oracle; batches, sessions and
+    strengths per block are refused."""
+    import ctypes
+    import torch
+    rs = _rs()
+    r = RADARS["odd"]()
+    empty = scenes.Pixels(*(np.zeros(0, np.float32) for _ in range(5)))
+    assert np.all(_synth(r, empty, 1e-6) == 0)
+    for P in (1, 2049):
+        px = scenes.tiny_scene(440 + P, P, vmax=5.0)
+        rel, _ = errors(_synth(r, px, 1e-6), oracle.cube(r, px))
+        assert rel <= 1e-6 + GATE_FP32, (P, rel)
+    plan = rs.rs_cube_plan_nufft(r, 0, max_pixels=10, tolerance=1e-4)
+    d = rs.DevicePixels.from_host(scenes.tiny_scene(450, 10))
+    cubes = rs.new_cube(plan, count=2)
+    with pytest.raises(rs.RSError) as e:
+        rs.rs_beat_synthesize_batch(plan, [d, d], cubes)
+    assert e.value.status == rs.RS_E_UNSUPPORTED
+    sess = rs.Session(hbm_budget=1 << 28, max_slots=1)
+    with pytest.raises(rs.RSError) as e:
+        sess.submit(plan, d, cubes[0])
+    assert e.value.status == rs.RS_E_UNSUPPORTED
+    sess.close()
+    torch.cuda.synchronize()
+    st, keep = rs._radar_struct(dataclasses.replace(r, model=16))
+    h = ctypes.c_void_p()
+    assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st), 0, 10, 1e-6, ctypes.byref(h)) == rs.RS_E_UNSUPPORTED
+    assert "NUFFT" in plan.describe(10) or "nufft" in plan.describe(10)
