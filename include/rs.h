@@ -44,9 +44,13 @@
  *                         rs_cube_plan): relative L2 error vs the exact sum
  *                         of about the tolerance, float32 rounding
  *                         (~1e-6) below.  Work grows with P C w^2 +
- *                         C Ns L log, not P C Ns L.  The grid sums use
- *                         atomics: results vary in the last bits from run
- *                         to run.  Limits: Ns, L <= 2048, strengths
+ *                         C Ns L log, not P C Ns L.  The grid sums are
+ *                         formed in a fixed order (bitwise reproducible)
+ *                         while each 512-pixel block's box of grid cells
+ *                         fits 1,024 cells; larger boxes are added with
+ *                         atomics and then the last bits vary from run to
+ *                         run.  Workspace grows with P (8 KiB per block and
+ *                         channel).  Limits: Ns, L <= 2048, strengths
  *                         constant over the blocks, single-frame calls
  *                         only (batch and sessions: RS_E_UNSUPPORTED).
  *

@@ -27,13 +27,6 @@ __device__ __forceinline__ T rs_gload(const T *p, int64_t i)
     return ((const __attribute__((address_space(1))) T *)p)[i];
 }
 
-// The same for a complex float32 value (one 8-byte load).
-__device__ __forceinline__ float2 rs_gload2(const float2 *p, int64_t i)
-{
-    const unsigned long long v = rs_gload(reinterpret_cast<const unsigned long long *>(p), i);
-    return make_float2(__uint_as_float((unsigned)(v & 0xffffffffu)), __uint_as_float((unsigned)(v >> 32)));
-}
-
 // Fractional part v - floor(v), in [0, 1] (1 only by rounding of tiny
 // negative v).
 __device__ __forceinline__ double rs_frac(double v) { return v - __builtin_floor(v); }

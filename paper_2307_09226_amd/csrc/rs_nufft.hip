@@ -81,6 +81,14 @@ __device__ __forceinline__ void gatomic_add(float *p, float v)
 
 __device__ __forceinline__ int pmod(int a, int n) { return ((a % n) + n) % n; }
 
+// Global load of a complex float32 value (one 8-byte load; rs_gload cannot
+// copy the vector class out of the global address space).
+__device__ __forceinline__ float2 rs_gload2(const float2 *p, int64_t i)
+{
+    const unsigned long long v = rs_gload(reinterpret_cast<const unsigned long long *>(p), i);
+    return make_float2(__uint_as_float((unsigned)(v & 0xffffffffu)), __uint_as_float((unsigned)(v >> 32)));
+}
+
 // Kernel weight at offset t (cells) from the point; zero outside |t| <= w/2.
 template <int W>
 __device__ __forceinline__ float es_weight(float t, float beta)
