@@ -174,6 +174,21 @@ rs_status rs_cube_plan_nufft(const rs_radar *radar, rs_dtype dtype, int64_t max_
  * (0 <= P <= max_pixels).  Errors: RS_E_INVALID. */
 rs_status rs_plan_workspace_bytes(const rs_plan *plan, int64_t P, size_t *bytes);
 
+/* Chooses the matrix-core tile of `plan` by measurement: every tile shape
+ * built into the library (rows per wave x columns x waves: 64x128x4,
+ * 32x128x4, 32x128x8, 32x64x4, 32x64x8, 64x64x4, 64x64x8, 128x64x4)
+ * synthesises `pixels` into `cube` once to warm up and `reps` times timed
+ * with HIP events on `hip_stream`, and the shape with the smallest mean time
+ * is kept (the plan's own choice otherwise comes from a rule measured on the
+ * frame and batch workloads).  The call synchronises the stream and leaves
+ * the last synthesis in `cube`.  It changes the plan: call it before the
+ * plan is shared, never while other calls use it.  Plans of the other forms
+ * are left unchanged.  chosen (may be NULL) receives "WNxTLxNW" (an empty
+ * string for the other forms).
+ * Errors: as rs_beat_synthesize, RS_E_INVALID for reps < 1. */
+rs_status rs_plan_tune(rs_plan *plan, const rs_pixels *pixels, void *cube, int32_t reps,
+                       void *hip_stream, char *chosen, size_t chosen_len);
+
 /* Human-readable description of the plan (form, tile, chunking) into buf
  * (always NUL-terminated when len > 0).  Errors: RS_E_INVALID. */
 rs_status rs_plan_describe(const rs_plan *plan, int64_t P, char *buf, size_t len);

@@ -448,6 +448,73 @@ extern "C" rs_status rs_plan_describe(const rs_plan *pl, int64_t P, char *buf, s
     return RS_OK;
 }
 
+// ----------------------------------------------------------- tile tuning ----
+
+static void set_mfma_shape(rs_plan *pl, int wn, int tl, int nw)
+{
+    pl->wn = wn;
+    pl->tl = tl;
+    pl->nw = nw;
+    pl->tn = nw * wn;
+    pl->n_tiles = (pl->Ns + pl->tn - 1) / pl->tn;
+    pl->l_tiles = (pl->L + pl->tl - 1) / pl->tl;
+}
+
+extern "C" rs_status rs_plan_tune(rs_plan *pl, const rs_pixels *px, void *cube, int32_t reps, void *stream,
+                                  char *chosen, size_t chosen_len)
+{
+    if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
+    if (reps < 1) return rs_fail(RS_E_INVALID, "reps < 1");
+    if (!cube) return rs_fail(RS_E_INVALID, "cube is NULL");
+    rs_status s = rs_check_pixels(pl, px);
+    if (s != RS_OK) return s;
+    if (pl->form == RS_FORM_MFMA_SPLIT16) {
+        static const int shapes[][3] = {{64, 128, 4}, {32, 128, 4}, {32, 128, 8}, {32, 64, 4},
+                                        {32, 64, 8},  {64, 64, 4},  {64, 64, 8},  {128, 64, 4}};
+        device_guard g(pl->device);
+        if (g.st != RS_OK) return g.st;
+        hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return rs_fail(RS_E_DEVICE, "hipEventCreate failed");
+        }
+        const int wn0 = pl->wn, tl0 = pl->tl, nw0 = pl->nw;
+        int best = -1;
+        float best_ms = 0.f;
+        for (int i = 0; i < (int)(sizeof shapes / sizeof shapes[0]) && s == RS_OK; ++i) {
+            if (!rs_mfma_shape_supported(shapes[i][0], shapes[i][1], shapes[i][2])) continue;
+            set_mfma_shape(pl, shapes[i][0], shapes[i][1], shapes[i][2]);
+            if ((s = rs_beat_synthesize(pl, px, cube, stream)) != RS_OK) break;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps && s == RS_OK; ++r) s = rs_beat_synthesize(pl, px, cube, stream);
+            (void)hipEventRecord(e1, st);
+            float ms = 0.f;
+            if (s == RS_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                s = rs_fail(RS_E_DEVICE, "event timing failed");
+            if (s == RS_OK && (best < 0 || ms < best_ms)) {
+                best = i;
+                best_ms = ms;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (s != RS_OK || best < 0) {
+            set_mfma_shape(pl, wn0, tl0, nw0);
+            return s != RS_OK ? s : rs_fail(RS_E_UNSUPPORTED, "no tile shape could run");
+        }
+        set_mfma_shape(pl, shapes[best][0], shapes[best][1], shapes[best][2]);
+        // leave the cube computed with the chosen shape
+        if ((s = rs_beat_synthesize(pl, px, cube, stream)) != RS_OK) return s;
+        if (hipStreamSynchronize(st) != hipSuccess) return rs_fail(RS_E_DEVICE, "stream synchronisation failed");
+    }
+    if (chosen && chosen_len > 0) {
+        if (pl->form == RS_FORM_MFMA_SPLIT16) snprintf(chosen, chosen_len, "%dx%dx%d", pl->wn, pl->tl, pl->nw);
+        else chosen[0] = '\0';
+    }
+    return RS_OK;
+}
+
 // ------------------------------------------------------------ synthesis ----
 
 extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, void *cube,

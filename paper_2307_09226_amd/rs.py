@@ -94,6 +94,8 @@ SIGNATURES = {
                                           ctypes.c_double, ctypes.POINTER(_VP)]),
     "rs_plan_workspace_bytes": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
     "rs_plan_describe": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_char_p, ctypes.c_size_t]),
+    "rs_plan_tune": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, ctypes.c_int32, _VP,
+                                    ctypes.c_char_p, ctypes.c_size_t]),
     "rs_beat_synthesize": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP]),
     "rs_beat_synthesize_ws": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP,
                                              ctypes.c_size_t, _VP]),
@@ -275,6 +277,16 @@ def new_cube(plan: Plan, device="cuda:0", count: Optional[int] = None):
     import torch
     shape = plan.cube_shape if count is None else (count,) + plan.cube_shape
     return torch.empty(shape, dtype=plan.torch_dtype, device=device)
+
+
+def rs_plan_tune(plan: Plan, pixels: DevicePixels, cube, reps: int = 3, stream=None) -> str:
+    """Times every matrix-core tile shape on these pixels and keeps the
+    fastest in the plan; returns it as "WNxTLxNW"."""
+    ps = pixels.struct(plan)
+    buf = ctypes.create_string_buffer(32)
+    _check(lib.rs_plan_tune(plan.handle, ctypes.byref(ps), _ptr(cube), int(reps), _stream_handle(stream),
+                            buf, 32))
+    return buf.value.decode()
 
 
 def rs_beat_synthesize(plan: Plan, pixels: DevicePixels, cube, stream=None):

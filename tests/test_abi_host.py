@@ -98,3 +98,8 @@ def test_nufft_plan_arguments_rejected_on_host():
         st2, keep2 = rs._radar_struct(dataclasses.replace(r, **kw))
         assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st2), 0, 10, 1e-6, ctypes.byref(h)) == code, kw
         assert rs.lib.rs_cube_plan(ctypes.byref(st2), rs.RS_FORM_NUFFT, 0, 10, ctypes.byref(h)) == code, kw
+
+
+def test_tune_arguments_rejected_on_host():
+    from paper_2307_09226_amd import rs
+    assert rs.lib.rs_plan_tune(None, None, None, 3, None, None, 0) == rs.RS_E_INVALID

@@ -1,0 +1,51 @@
+"""Tile tuning by measurement (rs_plan_tune): the chosen shape is one the
+library builds, the plan describes it, and cubes computed with it still
+match the oracle."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_09226_amd import scenes
+from gpu_util import GATE_MFMA, errors, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {"64x128x4", "32x128x4", "32x128x8", "32x64x4", "32x64x8", "64x64x4", "64x64x8", "128x64x4"}
+
+
+def test_tune_picks_a_built_shape_and_keeps_parity():
+    import torch
+    from paper_2307_09226_amd import rs
+    radar = scenes.radar_for(3, 4, 256, 64, Fs=10e6, Tb=120e-6)
+    px = scenes.tiny_scene(501, 9000, vmax=6.0)
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
+    d = rs.DevicePixels.from_host(px)
+    cube = rs.new_cube(plan)
+    chosen = rs.rs_plan_tune(plan, d, cube, reps=2)
+    print("tuned tile", chosen, flush=True)
+    assert chosen in SHAPES
+    desc = json.loads(plan.describe(px.P))
+    assert f"{desc['wave_rows']}x{desc['tile_l']}x{desc['waves']}" == chosen
+    # the cube left by the tuning call and a fresh one both match the oracle
+    c, l, n = sample_indices(radar.cube_shape(), 200, seed=5)
+    ref = oracle.entries(radar, px, c, l, n)
+    for got in (cube.cpu().numpy(), None):
+        if got is None:
+            out = rs.new_cube(plan)
+            rs.rs_beat_synthesize(plan, d, out)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+        rel, mx = errors(got[c, l, n], ref)
+        assert rel <= GATE_MFMA and mx <= GATE_MFMA
+
+
+def test_tune_leaves_other_forms_alone():
+    from paper_2307_09226_amd import rs
+    radar = scenes.radar_small()
+    px = scenes.tiny_scene(502, 100)
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_FP64_DIRECT, rs.RS_C64, max_pixels=px.P)
+    before = plan.describe(px.P)
+    rs.rs_plan_tune(plan, rs.DevicePixels.from_host(px), rs.new_cube(plan), reps=1)
+    assert plan.describe(px.P) == before
