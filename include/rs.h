@@ -46,7 +46,7 @@
  *                         (~1e-6) below.  Work grows with P C w^2 +
  *                         C Ns L log, not P C Ns L.  The grid sums are
  *                         formed in a fixed order (bitwise reproducible)
- *                         while each 512-pixel block's box of grid cells
+ *                         while each 256-pixel block's box of grid cells
  *                         fits 1,024 cells; larger boxes are added with
  *                         atomics and then the last bits vary from run to
  *                         run.  Workspace grows with P (8 KiB per block and

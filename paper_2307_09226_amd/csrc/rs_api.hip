@@ -434,7 +434,7 @@ extern "C" rs_status rs_plan_describe(const rs_plan *pl, int64_t P, char *buf, s
                  "\"tolerance\": %.3g, \"kernel_width\": %d, \"kernel_beta\": %.4g, \"grid_n\": %d, "
                  "\"grid_l\": %d, \"pixel_blocks\": %lld, \"cus\": %d, \"model\": %d}",
                  pl->dtype == RS_C128 ? "complex128" : "complex64", pl->C, pl->Ns, pl->L, pl->nu_tol, pl->nu_w,
-                 pl->nu_beta, pl->nu_n1, pl->nu_n2, (long long)((P + 511) / 512), pl->ncu, pl->model);
+                 pl->nu_beta, pl->nu_n1, pl->nu_n2, (long long)((P + 255) / 256), pl->ncu, pl->model);
         return RS_OK;
     }
     snprintf(buf, len,

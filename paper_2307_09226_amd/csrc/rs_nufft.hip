@@ -11,7 +11,7 @@
 // phi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1)) of width w cells, grid
 // oversampled at least twofold):
 //   k_nufft_zero    clear the n1 x n2 grid of every channel
-//   k_nufft_spread  per (block of 512 pixels, channel): phase arguments in
+//   k_nufft_spread  per (block of 256 pixels, channel): phase arguments in
 //                   binary64 (the same recipe as the direct forms), reduced
 //                   frequencies u' = u - rint(u), v' = v - rint(v), centring
 //                   phase exp(j2pi (u' floor(Ns/2) + v' floor(L/2))), and the
@@ -46,8 +46,8 @@
 namespace {
 
 constexpr int kSpreadThreads = 256;
-constexpr int kBlockPts = 512;                        // pixels per spreading workgroup (power of two)
-constexpr int kMaxCols = 2048;                        // widest box gathered per cell
+constexpr int kBlockPts = 256;                        // pixels per spreading workgroup (power of two)
+constexpr int kMaxCols = 1024;                        // widest box gathered per cell
 constexpr int kSlot = 1024;                           // tile cells kept per (block, channel)
 constexpr int kMaskBlocks = 1024;                     // blocks per coverage pass of a row
 constexpr int kSplit = 4;                             // threads per cell in the assembly
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     __shared__ float pw1[kBlockPts * W], pw2[kBlockPts * W];
     __shared__ int key[kBlockPts];
     __shared__ int cs[kMaxCols + 1];
-    __shared__ int4 srec[kBlockPts];      // sorted: (m1 - lo1, m2 - lo2, point index, 0)
+    __shared__ int2 srec[kBlockPts];      // sorted: ((m1 - lo1) | (m2 - lo2) << 16, point index)
     __shared__ float2 spc[kBlockPts];     // sorted strengths
     __shared__ int red[kSpreadThreads / 64];
     const int tid = threadIdx.x;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     const int ncol = hi1 - lo1 + 1;
     for (int s = tid; s < npts; s += kSpreadThreads) {
         const int q = key[s] % kBlockPts;
-        srec[s] = make_int4(pm1[q] - lo1, pm2[q] - lo2, q, 0);
+        srec[s] = make_int2((pm1[q] - lo1) | ((pm2[q] - lo2) << 16), q);
         spc[s] = pc[q];
         const int col = key[s] / kBlockPts;
         const int prev = s == 0 ? -1 : key[s - 1] / kBlockPts;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
         // of this column range have dx in [0, W) by construction
         constexpr int kU = 8;
         for (int s0 = sb; s0 < se; s0 += kU) {
-            int4 rec[kU];
+            int2 rec[kU];
             float2 cv[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
@@ -273,9 +273,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
             float w1v[kU], w2v[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int dx = x - rec[u].x, dy = y - rec[u].y;
+                const int dx = x - (rec[u].x & 0xffff), dy = y - (rec[u].x >> 16);
                 const bool hit = s0 + u < se && dy >= 0 && dy < W;
-                const int base = rec[u].z * W;
+                const int base = rec[u].y * W;
                 w1v[u] = pw1[base + (hit ? dx : 0)];
                 w2v[u] = hit ? pw2[base + dy] : 0.f;
             }
