@@ -52,6 +52,7 @@ constexpr int kSlot = 1024;                           // tile cells kept per (bl
 constexpr int kMaskBlocks = 1024;                     // blocks per coverage pass of a row
 constexpr int kSplit = 4;                             // threads per cell in the assembly
 constexpr int kAsmCols = 256 / kSplit;                // grid columns per assembly workgroup
+constexpr int kAsmRows = 8;                           // grid rows per assembly workgroup
 constexpr int kFftThreads = 256;
 constexpr int kFftElems = 4096;                       // complex values per FFT workgroup
 
@@ -79,7 +80,9 @@ __device__ __forceinline__ void gatomic_add(float *p, float v)
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int pmod(int a, int n) { return ((a % n) + n) % n; }
+// a mod n in [0, n) for the grid sizes, which are powers of two (two's
+// complement makes the mask right for negative a too)
+__device__ __forceinline__ int pmod(int a, int n) { return a & (n - 1); }
 
 // Global load of a complex float32 value (one 8-byte load; rs_gload cannot
 // copy the vector class out of the global address space).
@@ -297,9 +300,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     }
 }
 
-// Adds the tile slots to the grid: a workgroup per (channel, grid row, 64
-// columns), four threads per cell.  The blocks whose box covers the row are
-// listed in LDS in block order (a coverage bitmask, set in any order, read in
+// Adds the tile slots to the grid: a workgroup per (channel, 8 grid rows n2/8
+// apart, 64 columns), four threads per cell.  The blocks whose box covers the row and
+// overlaps the workgroup's columns are listed in LDS in block order (a coverage bitmask, set in any order, read in
 // order), and every cell sums its tiles in that order, so the result does
 // not depend on scheduling.  Rows no slot covers (their flag, set by the
 // spreading kernel, is zero) return at once.
@@ -312,85 +315,96 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
     __shared__ int lid[kMaskBlocks];
     __shared__ int ncov;
     __shared__ float2 part[kSplit][kAsmCols];
-    const int c = blockIdx.z, m2 = blockIdx.y;
-    if (rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) == 0) return;   // no slot covers this row
+    const int c = blockIdx.z;
     // thread = (column, quarter of the covering list): the four partial sums
     // of a cell are added in a fixed order at the end
     const int lc = threadIdx.x % kAsmCols, sp = threadIdx.x / kAsmCols;
-    const int col = blockIdx.x * kAsmCols + lc;
+    const int c0 = blockIdx.x * kAsmCols;
+    const int col = c0 + lc;
     const int4 *dc = A.desc + (int64_t)c * A.nblk;
     const float2 *tc = A.tiles + (int64_t)c * A.nblk * kSlot;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int b0 = 0; b0 < A.nblk; b0 += kMaskBlocks) {
-        const int nb = min(kMaskBlocks, A.nblk - b0);
-        const int nw = (nb + 31) / 32;
-        for (int w = threadIdx.x; w < nw; w += blockDim.x) mask[w] = 0u;
-        __syncthreads();
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int4 d = dc[b0 + b];
-            if (d.z > 0 && pmod(m2 - d.y, A.n2) < d.w) atomicOr(&mask[b >> 5], 1u << (b & 31));
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int o = 0;
-            for (int w = 0; w < nw; ++w) {
-                woff[w] = o;
-                o += __builtin_popcount(mask[w]);
-            }
-            ncov = o;
-        }
-        __syncthreads();
-        const int nc = ncov;
-        if (nc > 0) {
-            for (int w = threadIdx.x; w < nw; w += blockDim.x) {
-                unsigned bits = mask[w];
-                int o = woff[w];
-                while (bits) {
-                    const int b = b0 + w * 32 + __builtin_ctz(bits);
-                    bits &= bits - 1u;
-                    lid[o] = b;
-                    ldesc[o] = dc[b];
-                    ++o;
-                }
+    // rows blockIdx.y + k gridDim.y: the covered rows, which lie together
+    // around the scene's Doppler band, go to different workgroups
+    for (int m2 = blockIdx.y; m2 < A.n2; m2 += gridDim.y) {
+        if (rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) == 0) continue;   // no slot covers this row (uniform)
+        float2 acc = make_float2(0.f, 0.f);
+        for (int b0 = 0; b0 < A.nblk; b0 += kMaskBlocks) {
+            const int nb = min(kMaskBlocks, A.nblk - b0);
+            const int nw = (nb + 31) / 32;
+            for (int w = threadIdx.x; w < nw; w += blockDim.x) mask[w] = 0u;
+            __syncthreads();
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+                const int4 d = dc[b0 + b];
+                // the box covers this row and overlaps this workgroup's columns
+                // c0 .. c0 + kAsmCols - 1 (both taken around the periodic grid)
+                if (d.z > 0 && pmod(m2 - d.y, A.n2) < d.w &&
+                    (pmod(c0 - d.x, A.n1) < d.z || pmod(d.x - c0, A.n1) < kAsmCols))
+                    atomicOr(&mask[b >> 5], 1u << (b & 31));
             }
             __syncthreads();
-            if (col < A.n1) {
-                const int kb = (int)((int64_t)nc * sp / kSplit), ke = (int)((int64_t)nc * (sp + 1) / kSplit);
-                // kU covering blocks per round: their tile loads are in flight together
-                constexpr int kU = 8;
-                for (int k0 = kb; k0 < ke; k0 += kU) {
-                    float2 t[kU];
-#pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        t[u] = make_float2(0.f, 0.f);
-                        if (k0 + u < ke) {
-                            const int4 d = ldesc[k0 + u];
-                            const int xx = pmod(col - d.x, A.n1);
-                            if (xx < d.z)
-                                t[u] = rs_gload2(tc + (int64_t)lid[k0 + u] * kSlot, pmod(m2 - d.y, A.n2) * d.z + xx);
-                        }
+            if (threadIdx.x == 0) {
+                int o = 0;
+                for (int w = 0; w < nw; ++w) {
+                    woff[w] = o;
+                    o += __builtin_popcount(mask[w]);
+                }
+                ncov = o;
+            }
+            __syncthreads();
+            const int nc = ncov;
+            if (nc > 0) {
+                for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+                    unsigned bits = mask[w];
+                    int o = woff[w];
+                    while (bits) {
+                        const int b = b0 + w * 32 + __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        lid[o] = b;
+                        ldesc[o] = dc[b];
+                        ++o;
                     }
+                }
+                __syncthreads();
+                if (col < A.n1) {
+                    const int kb = (int)((int64_t)nc * sp / kSplit), ke = (int)((int64_t)nc * (sp + 1) / kSplit);
+                    // kU covering blocks per round: their tile loads are in flight together
+                    constexpr int kU = 8;
+                    for (int k0 = kb; k0 < ke; k0 += kU) {
+                        float2 t[kU];
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) {
-                        acc.x += t[u].x;
-                        acc.y += t[u].y;
+                        for (int u = 0; u < kU; ++u) {
+                            t[u] = make_float2(0.f, 0.f);
+                            if (k0 + u < ke) {
+                                const int4 d = ldesc[k0 + u];
+                                const int xx = pmod(col - d.x, A.n1);
+                                if (xx < d.z)
+                                    t[u] = rs_gload2(tc + (int64_t)lid[k0 + u] * kSlot,
+                                                     pmod(m2 - d.y, A.n2) * d.z + xx);
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < kU; ++u) {
+                            acc.x += t[u].x;
+                            acc.y += t[u].y;
+                        }
                     }
                 }
             }
+            __syncthreads();   // mask and list are rebuilt for the next block range
         }
-        __syncthreads();   // mask and list are rebuilt for the next block range
-    }
-    part[sp][lc] = acc;
-    __syncthreads();
-    if (sp == 0 && col < A.n1) {
-        float2 *g = A.grid + ((int64_t)c * A.n2 + m2) * A.n1 + col;
-        float2 v = rs_gload2(g, 0);
+        part[sp][lc] = acc;
+        __syncthreads();
+        if (sp == 0 && col < A.n1) {
+            float2 *g = A.grid + ((int64_t)c * A.n2 + m2) * A.n1 + col;
+            float2 v = rs_gload2(g, 0);
 #pragma unroll
-        for (int k = 0; k < kSplit; ++k) {
-            v.x += part[k][lc].x;
-            v.y += part[k][lc].y;
+            for (int k = 0; k < kSplit; ++k) {
+                v.x += part[k][lc].x;
+                v.y += part[k][lc].y;
+            }
+            *g = v;
         }
-        *g = v;
+        __syncthreads();   // part is rewritten for the next row
     }
 }
 
@@ -604,7 +618,7 @@ rs_status rs_nufft_enqueue(const rs_plan *pl, const rs_pixels *px, void *cube, v
     }
     if (A.nblk > 0)
         hipLaunchKernelGGL(k_nufft_assemble, dim3((unsigned)((pl->nu_n1 + kAsmCols - 1) / kAsmCols),
-                                                  (unsigned)pl->nu_n2, (unsigned)pl->C),
+                                                  (unsigned)std::max(1, pl->nu_n2 / kAsmRows), (unsigned)pl->C),
                            dim3(kFftThreads), 0, st, A);
     const int logn1 = log2i(pl->nu_n1), logn2 = log2i(pl->nu_n2);
     const int rpw = std::max(1, kFftElems / pl->nu_n1);
