@@ -67,6 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_doppler_power(const float2 *rf, fl
 {
     extern __shared__ float2 smem[];
     const int L = 1 << logl;
+    const int logkb = __builtin_ctz((unsigned)kb);
     const int groups = Ns / kb;
     const int f = blockIdx.x / groups;
     const int k0 = (blockIdx.x % groups) * kb;
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_doppler_power(const float2 *rf, fl
         const float2 *src = rf + (((int64_t)f * C + c) * L) * Ns + k0;
         // element e = l * kb + kk: kb consecutive range bins of one block row
         for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-            const int l = e / kb, kk = e % kb;
+            const int l = e >> logkb, kk = e & (kb - 1);   // kb is a power of two
             x[kk * L + bitrev(l, logl)] = src[(int64_t)l * Ns + kk];
         }
         __syncthreads();
