@@ -49,6 +49,8 @@ constexpr int kSpreadThreads = 256;
 constexpr int kBlockPts = 256;                        // pixels per spreading workgroup (power of two)
 constexpr int kMaxCols = 1024;                        // widest box gathered per cell
 constexpr int kSlot = 1024;                           // tile cells kept per (block, channel)
+constexpr int kAccCells = 2048;                       // LDS accumulator cells of the column gather
+constexpr int kRowsReg = 16;                          // box rows held in registers by the column gather
 constexpr int kMaskBlocks = 1024;                     // blocks per coverage pass of a row
 constexpr int kSplit = 4;                             // threads per cell in the assembly
 constexpr int kAsmCols = 256 / kSplit;                // grid columns per assembly workgroup
@@ -146,6 +148,10 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     __shared__ int cs[kMaxCols + 1];
     __shared__ int2 srec[kBlockPts];      // sorted: ((m1 - lo1) | (m2 - lo2) << 16, point index)
     __shared__ float2 spc[kBlockPts];     // sorted strengths
+    // per-share accumulators [share][row][column]; before them, in the same
+    // space, each sorted point's w2 placed at its row of the box (16 rows)
+    __shared__ __align__(16) float accbuf[2 * kAccCells];   // read as float4
+    float *accr = accbuf, *acci = accbuf + kAccCells, *spw2r = accbuf;
     __shared__ int red[kSpreadThreads / 64];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
@@ -255,7 +261,116 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     }
     __syncthreads();
 
-    // ---- 3. gather per cell, one atomic pair per nonzero cell ---------------
+    // ---- 3a. boxes that fit a tile slot: a thread per (column, share of its
+    // candidates) forms c w1 once per point and adds c w1 w2[j] to the W rows
+    // of its private LDS accumulator; the shares are then added in a fixed
+    // order per cell ---------------------------------------------------------
+    const int E = e1 * e2;
+    const int nparts = slot ? min(kSpreadThreads / e1, kAccCells / E) : 0;
+    if (nparts > 0 && e2 <= kRowsReg) {
+        // boxes of at most 16 rows: the row sums of a column live in
+        // registers, and each point's w2 is laid out at its row offset once
+        // per block so that a candidate costs four LDS vector reads and 32 FMAs
+        for (int k = tid; k < npts * kRowsReg; k += kSpreadThreads) {
+            const int s = k / kRowsReg, rr = k % kRowsReg;
+            const int2 rec = srec[s];
+            const int d = rr - (rec.x >> 16);
+            spw2r[k] = d >= 0 && d < W ? pw2[rec.y * W + d] : 0.f;
+        }
+        __syncthreads();
+        const int x = tid % e1, p = tid / e1;
+        float ar[kRowsReg], ai[kRowsReg];
+#pragma unroll
+        for (int r = 0; r < kRowsReg; ++r) ar[r] = ai[r] = 0.f;
+        if (p < nparts) {
+            const int k0 = max(0, x - W + 1), k1 = min(x, ncol - 1);
+            const int sb = cs[k0], len = cs[k1 + 1] - sb;
+            const int s_beg = sb + len * p / nparts, s_end = sb + len * (p + 1) / nparts;
+            for (int s = s_beg; s < s_end; ++s) {
+                const int2 rec = srec[s];
+                const float2 cv = spc[s];
+                const float w1 = pw1[rec.y * W + x - (rec.x & 0xffff)];   // dx in [0, W) for this column range
+                const float cr = cv.x * w1, ci = cv.y * w1;
+                const float4 *wv = reinterpret_cast<const float4 *>(spw2r + s * kRowsReg);
+#pragma unroll
+                for (int r4 = 0; r4 < kRowsReg / 4; ++r4) {
+                    const float4 w = wv[r4];
+                    ar[4 * r4 + 0] = __builtin_fmaf(cr, w.x, ar[4 * r4 + 0]);
+                    ai[4 * r4 + 0] = __builtin_fmaf(ci, w.x, ai[4 * r4 + 0]);
+                    ar[4 * r4 + 1] = __builtin_fmaf(cr, w.y, ar[4 * r4 + 1]);
+                    ai[4 * r4 + 1] = __builtin_fmaf(ci, w.y, ai[4 * r4 + 1]);
+                    ar[4 * r4 + 2] = __builtin_fmaf(cr, w.z, ar[4 * r4 + 2]);
+                    ai[4 * r4 + 2] = __builtin_fmaf(ci, w.z, ai[4 * r4 + 2]);
+                    ar[4 * r4 + 3] = __builtin_fmaf(cr, w.w, ar[4 * r4 + 3]);
+                    ai[4 * r4 + 3] = __builtin_fmaf(ci, w.w, ai[4 * r4 + 3]);
+                }
+            }
+        }
+        __syncthreads();   // spw2r is overwritten by the accumulators below
+        if (p < nparts) {
+#pragma unroll
+            for (int r = 0; r < kRowsReg; ++r) {
+                if (r < e2) {
+                    accr[p * E + r * e1 + x] = ar[r];
+                    acci[p * E + r * e1 + x] = ai[r];
+                }
+            }
+        }
+        __syncthreads();
+        float2 *slotp = A.tiles + ((int64_t)c * A.nblk + blockIdx.x) * kSlot;
+        for (int cell = tid; cell < E; cell += kSpreadThreads) {
+            float sr = 0.f, si = 0.f;
+            for (int q = 0; q < nparts; ++q) {
+                sr += accr[q * E + cell];
+                si += acci[q * E + cell];
+            }
+            slotp[cell] = make_float2(sr, si);   // the assembly adds the slot to the grid rows it covers
+        }
+        return;
+    }
+    if (nparts > 0) {
+        for (int k = tid; k < nparts * E; k += kSpreadThreads) {
+            accr[k] = 0.f;
+            acci[k] = 0.f;
+        }
+        __syncthreads();
+        const int x = tid % e1, p = tid / e1;
+        if (p < nparts) {
+            const int k0 = max(0, x - W + 1), k1 = min(x, ncol - 1);
+            const int sb = cs[k0], len = cs[k1 + 1] - sb;
+            const int s_beg = sb + len * p / nparts, s_end = sb + len * (p + 1) / nparts;
+            float *ar = accr + p * E + x, *ai = acci + p * E + x;
+            for (int s = s_beg; s < s_end; ++s) {
+                const int2 rec = srec[s];
+                const float2 cv = spc[s];
+                const int base = rec.y * W;
+                const float w1 = pw1[base + x - (rec.x & 0xffff)];   // dx in [0, W) for this column range
+                const float cr = cv.x * w1, ci = cv.y * w1;
+                const int r0 = (rec.x >> 16) * e1;
+                float w2[W];
+#pragma unroll
+                for (int j = 0; j < W; ++j) w2[j] = pw2[base + j];
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    ar[r0 + j * e1] = __builtin_fmaf(cr, w2[j], ar[r0 + j * e1]);
+                    ai[r0 + j * e1] = __builtin_fmaf(ci, w2[j], ai[r0 + j * e1]);
+                }
+            }
+        }
+        __syncthreads();
+        float2 *slotp = A.tiles + ((int64_t)c * A.nblk + blockIdx.x) * kSlot;
+        for (int cell = tid; cell < E; cell += kSpreadThreads) {
+            float sr = 0.f, si = 0.f;
+            for (int q = 0; q < nparts; ++q) {
+                sr += accr[q * E + cell];
+                si += acci[q * E + cell];
+            }
+            slotp[cell] = make_float2(sr, si);   // the assembly adds the slot to the grid rows it covers
+        }
+        return;
+    }
+
+    // ---- 3b. other boxes: gather per cell, one atomic pair per nonzero cell -
     for (int cell = tid; cell < e1 * e2; cell += kSpreadThreads) {
         const int y = cell / e1, x = cell - y * e1;
         const int k0 = max(0, x - W + 1), k1 = min(x, ncol - 1);
@@ -290,7 +405,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
             }
         }
         if (slot) {
-            // the row-FFT kernel adds the slot to the grid rows it covers
+            // the assembly adds the slot to the grid rows it covers
             A.tiles[((int64_t)c * A.nblk + blockIdx.x) * kSlot + cell] = make_float2(sr, si);
         } else if (sr != 0.f || si != 0.f) {
             float2 *g = grid + (int64_t)pmod(lo2 + y, A.n2) * A.n1 + pmod(lo1 + x, A.n1);
@@ -301,11 +416,12 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
 }
 
 // Adds the tile slots to the grid: a workgroup per (channel, 8 grid rows n2/8
-// apart, 64 columns), four threads per cell.  The blocks whose box covers the row and
-// overlaps the workgroup's columns are listed in LDS in block order (a coverage bitmask, set in any order, read in
-// order), and every cell sums its tiles in that order, so the result does
-// not depend on scheduling.  Rows no slot covers (their flag, set by the
-// spreading kernel, is zero) return at once.
+// apart, 64 columns), four threads per cell.  The blocks whose box covers the
+// row and overlaps the workgroup's columns are listed in LDS in block order
+// (a coverage bitmask, set in any order, read in order), and every cell sums
+// its tiles in that order, so the result does not depend on scheduling.
+// Rows no slot covers (their flag, set by the spreading kernel, is zero)
+// are skipped.
 __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
 {
     constexpr int kWords = kMaskBlocks / 32;
