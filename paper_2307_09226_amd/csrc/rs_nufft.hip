@@ -26,11 +26,13 @@
 //                   sum, in block order, a quarter each of the tiles whose box
 //                   covers it, and the quarters are added in a fixed order (no
 //                   atomics on the cells every block touches)
-//   k_nufft_rows    FFT (+ sign) of every grid row of length n1 in LDS; the
-//                   Ns kept modes times the deconvolution factor h / phi_hat
-//                   go to a row buffer [C][n2][Ns]
-//   k_nufft_cols    FFT (+ sign) of every column of length n2, the L kept
-//                   modes times their deconvolution factor into the cube
+//   k_nufft_rows    FFT (+ sign) of every grid row of length n1 in LDS that
+//                   some block wrote to; the Ns kept modes times the
+//                   deconvolution factor h / phi_hat go to a row buffer
+//                   [C][n2][Ns]
+//   k_nufft_cols    FFT (+ sign) of every column of length n2 (rows no block
+//                   wrote to read as zero), the L kept modes times their
+//                   deconvolution factor into the cube
 // Arithmetic: phase arguments binary64; strengths, weights, grid and FFTs
 // float32.  The sums are formed in a fixed order when every box fits a tile
 // slot; boxes that do not are added with atomics, and then the order of the
@@ -70,7 +72,7 @@ struct nu_args {
     float2 *rows;               // [C][n2][Ns]
     float2 *tiles;              // [C][nblk][kSlot]: each block's box sums, row-major e1 x e2
     int4 *desc;                 // [C][nblk]: box (lo1, lo2, e1, e2); e1 = 0 when not in a slot
-    int *rowcov;                // [C][n2]: nonzero when some slot covers the grid row
+    int *rowcov;                // [C][n2]: nonzero when some block wrote to the grid row
     int32_t nblk;               // pixel blocks
     const float *d1, *d2;       // deconvolution factors [Ns], [L]
     void *cube;                 // [C][L][Ns]
@@ -208,7 +210,10 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     int4 *dsc = A.desc + (int64_t)c * A.nblk + blockIdx.x;
     const bool slot = e1 * e2 <= kSlot && hi1 - lo1 < kMaxCols && e1 <= A.n1 && e2 <= A.n2;
     if (tid == 0) *dsc = make_int4(lo1, lo2, slot ? e1 : 0, e2);
-    if (slot && tid < e2) atomicOr(A.rowcov + (int64_t)c * A.n2 + pmod(lo2 + tid, A.n2), 1);
+    // flag the grid rows this block writes to (every row when the box is
+    // taller than the grid): the FFT passes skip the rows no block touches
+    for (int t = tid; t < min(e2, A.n2); t += kSpreadThreads)
+        atomicOr(A.rowcov + (int64_t)c * A.n2 + pmod(lo2 + t, A.n2), 1);
     if (hi1 - lo1 >= kMaxCols || e1 > A.n1 || e2 > A.n2) {
         // box wider than the grid or the column table: scatter each weight
         // to the grid (a lane per window cell, a wave per point)
@@ -420,7 +425,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
 // row and overlaps the workgroup's columns are listed in LDS in block order
 // (a coverage bitmask, set in any order, read in order), and every cell sums
 // its tiles in that order, so the result does not depend on scheduling.
-// Rows no slot covers (their flag, set by the spreading kernel, is zero)
+// Rows no block wrote to (their flag, set by the spreading kernel, is zero)
 // are skipped.
 __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
 {
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
     // rows blockIdx.y + k gridDim.y: the covered rows, which lie together
     // around the scene's Doppler band, go to different workgroups
     for (int m2 = blockIdx.y; m2 < A.n2; m2 += gridDim.y) {
-        if (rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) == 0) continue;   // no slot covers this row (uniform)
+        if (rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) == 0) continue;   // no block wrote to this row (uniform)
         float2 acc = make_float2(0.f, 0.f);
         for (int b0 = 0; b0 < A.nblk; b0 += kMaskBlocks) {
             const int nb = min(kMaskBlocks, A.nblk - b0);
@@ -535,11 +540,20 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_rows(nu_args A, int logn1
     const int64_t r0 = (int64_t)blockIdx.x * rpw;
     const int rows = (int)min<int64_t>(rpw, rows_total - r0);
     if (rows <= 0) return;
+    // grid rows no block touched are zero, and so are their transforms: the
+    // column pass reads them as zero, so they are neither read nor written
+    __shared__ int live[kFftElems / 16];   // rows per workgroup <= kFftElems / 16 (n1 >= 16)
+    int mine = 0;
+    for (int row = threadIdx.x; row < rows; row += blockDim.x) {
+        live[row] = rs_gload(A.rowcov, r0 + row);
+        mine |= live[row];
+    }
+    if (!__syncthreads_or(mine)) return;
     twiddles(tw, n1, +1.0);
     const float2 *src = A.grid + r0 * n1;
     for (int e = threadIdx.x; e < rows * n1; e += blockDim.x) {
         const int row = e >> logn1, col = e & (n1 - 1);
-        x[row * n1 + bitrev(col, logn1)] = rs_gload2(src, e);
+        x[row * n1 + bitrev(col, logn1)] = live[row] ? rs_gload2(src, e) : make_float2(0.f, 0.f);
     }
     __syncthreads();
     fft_rows(x, rows, logn1, tw);
@@ -547,6 +561,7 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_rows(nu_args A, int logn1
     float2 *dst = A.rows + r0 * A.Ns;
     for (int e = threadIdx.x; e < rows * A.Ns; e += blockDim.x) {
         const int row = e / A.Ns, n = e - row * A.Ns;
+        if (!live[row]) continue;
         const int k = n - h;
         const float2 v = x[row * n1 + (k < 0 ? k + n1 : k)];
         const float d = rs_gload(A.d1, n);
@@ -566,18 +581,24 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_cols(nu_args A, int logn2
     const int c = blockIdx.x / groups;
     const int n0 = (blockIdx.x % groups) * kb;
     const int kn = min(kb, A.Ns - n0);
+    const int logkb = __builtin_ctz((unsigned)kb);   // kb is a power of two
+    __shared__ int live[kFftElems];        // grid rows of this channel some block wrote to (n2 <= kFftElems)
+    for (int m2 = threadIdx.x; m2 < n2; m2 += blockDim.x) live[m2] = rs_gload(A.rowcov, (int64_t)c * n2 + m2);
     twiddles(tw, n2, +1.0);
+    __syncthreads();
     const float2 *src = A.rows + (int64_t)c * n2 * A.Ns + n0;
     for (int e = threadIdx.x; e < n2 * kb; e += blockDim.x) {
-        const int m2 = e / kb, kk = e - m2 * kb;
-        x[kk * n2 + bitrev(m2, logn2)] = kk < kn ? rs_gload2(src, (int64_t)m2 * A.Ns + kk) : make_float2(0.f, 0.f);
+        const int m2 = e >> logkb, kk = e & (kb - 1);
+        // untouched rows are zero (their row-buffer entries were never written)
+        x[kk * n2 + bitrev(m2, logn2)] =
+            kk < kn && live[m2] ? rs_gload2(src, (int64_t)m2 * A.Ns + kk) : make_float2(0.f, 0.f);
     }
     __syncthreads();
     fft_rows(x, kb, logn2, tw);
     const int h = A.L / 2;
     OT *out = reinterpret_cast<OT *>(A.cube) + (int64_t)c * A.L * A.Ns + n0;
     for (int e = threadIdx.x; e < A.L * kb; e += blockDim.x) {
-        const int l = e / kb, kk = e - l * kb;
+        const int l = e >> logkb, kk = e & (kb - 1);
         if (kk >= kn) continue;
         const int k = l - h;
         const float2 v = x[kk * n2 + (k < 0 ? k + n2 : k)];
