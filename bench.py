@@ -264,6 +264,27 @@ def main():
             }
             del ncube
             nplan.close()
+        # the largest serving-size request (12 x 16 array, 192 channels): the
+        # NUFFT's work grows with P C w^2, the direct sum's with P C Ns L
+        big = max((q for q in scenes.serving_requests(48) if q.radar.C == 192),
+                  key=lambda q: q.pixels.P * q.radar.Ns * q.radar.L)
+        bterms = big.pixels.P * big.radar.C * big.radar.Ns * big.radar.L
+        bd = rs.DevicePixels.from_host(big.pixels, dev)
+        bn = rs.rs_cube_plan_nufft(big.radar, rs.RS_C64, max_pixels=big.pixels.P, tolerance=1e-6)
+        bm = rs.rs_cube_plan(big.radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=big.pixels.P)
+        bcn, bcm = rs.new_cube(bn, dev), rs.new_cube(bm, dev)
+        nw, _ = timed_steps(lambda: rs.rs_beat_synthesize(bn, bd, bcn), 5, 2)
+        mw, _ = timed_steps(lambda: rs.rs_beat_synthesize(bm, bd, bcm), 3, 1)
+        torch.cuda.synchronize()
+        out["nufft"]["largest_request"] = {
+            "workload": f"{big.radar.M} Tx x {big.radar.N} Rx, Ns={big.radar.Ns}, L={big.radar.L}, "
+                        f"{big.pixels.P} pixels (terms {bterms:.3e})",
+            "nufft_ms": nw * 1e3 / 5, "mfma_ms": mw * 1e3 / 3, "speedup_vs_mfma": (mw / 3) / (nw / 5),
+            "parity_vs_exact": parity_sampled(big.radar, big.pixels, bcn.cpu().numpy(), k=128),
+        }
+        del bcn, bcm, bd
+        bn.close()
+        bm.close()
 
     if "batch" in legs:
         # ---- 64 animation frames in one persistent launch -------------------------
