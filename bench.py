@@ -141,9 +141,27 @@ def cpu_baseline(radar, px, seconds):
     rate = k0 * px.P / dt
     k = int(max(k0, min(200000, rate * seconds / px.P)))
     dt = run(k)
+    # one thread, on a sample of about three seconds
+    o1 = o
+    k1 = max(16, int(rate / max(cores, 1) * 3.0 / px.P))
+    c = rng.integers(0, C, k1).astype(np.int32)
+    l = rng.integers(0, L, k1).astype(np.int32)
+    n = rng.integers(0, Ns, k1).astype(np.int32)
+    t = time.perf_counter()
+    o1.entries(radar, px, c, l, n, threads=1)
+    dt1 = time.perf_counter() - t
+    o.max_threads(cores)   # the thread count is process-wide: restore it
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": k * px.P / dt, "unit": "terms/s", "cores": cores, "kind": "oracle",
             "sample": f"{k} seeded output entries of the headline frame, each summed over "
-                      f"all {px.P} pixels ({k * px.P:.3e} terms, {dt:.1f} s)"}
+                      f"all {px.P} pixels ({k * px.P:.3e} terms, {dt:.1f} s)",
+            "cpu_model": model, "value_one_thread": k1 * px.P / dt1,
+            "sample_one_thread": f"{k1} entries ({k1 * px.P:.3e} terms, {dt1:.1f} s)"}
 
 
 def main():
