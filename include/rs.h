@@ -166,7 +166,8 @@ rs_status rs_cube_plan(const rs_radar *radar, rs_form form, rs_dtype dtype,
  * w = ceil(log10(1/tolerance)) + 1 cells (at most 8), shape beta = 2.30 w,
  * grid the smallest power of two >= max(2 Ns, 2 w) by >= max(2 L, 2 w).
  * Errors: as rs_cube_plan, RS_E_INVALID for a tolerance outside the range,
- * RS_E_UNSUPPORTED for RS_MODEL_BLOCK_STRENGTH or Ns or L > 2048. */
+ * RS_E_UNSUPPORTED for RS_MODEL_BLOCK_STRENGTH, Ns or L > 2048, more than
+ * 65,535 channels or max_pixels >= 2^31. */
 rs_status rs_cube_plan_nufft(const rs_radar *radar, rs_dtype dtype, int64_t max_pixels,
                              double tolerance, rs_plan **out);
 

@@ -269,6 +269,8 @@ static rs_status plan_common(const rs_radar *r, rs_form form, rs_dtype dtype, in
             return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form needs strengths constant over the blocks");
         if (r->Ns > 2048 || r->L > 2048) return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves Ns, L <= 2048");
         if ((int64_t)r->M * r->N > 65535) return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves <= 65535 channels");
+        if (max_pixels > ((int64_t)1 << 31) - 1)
+            return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves max_pixels < 2^31");
     }
 
     rs_plan *pl = new (std::nothrow) rs_plan();

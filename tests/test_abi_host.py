@@ -98,6 +98,7 @@ def test_nufft_plan_arguments_rejected_on_host():
         st2, keep2 = rs._radar_struct(dataclasses.replace(r, **kw))
         assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st2), 0, 10, 1e-6, ctypes.byref(h)) == code, kw
         assert rs.lib.rs_cube_plan(ctypes.byref(st2), rs.RS_FORM_NUFFT, 0, 10, ctypes.byref(h)) == code, kw
+    assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st), 0, 1 << 31, 1e-6, ctypes.byref(h)) == rs.RS_E_UNSUPPORTED
 
 
 def test_tune_arguments_rejected_on_host():
