@@ -31,7 +31,7 @@ namespace {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-int round_up(int64_t v, int m) { return (int)(((v + m - 1) / m) * m); }
+int64_t round_up(int64_t v, int64_t m) { return ((v + m - 1) / m) * m; }
 
 }  // namespace
 

@@ -18,7 +18,9 @@
 //                   w x w kernel weights around (u' n1, v' n2); the points
 //                   are sorted by window column in LDS and every cell of the
 //                   block's bounding box gathers its sum in registers into
-//                   the block's tile slot (boxes of up to 1,024 cells);
+//                   the block's tile slot (boxes of up to 1,024 cells; a
+//                   box taller than 16 rows whose points form two row groups
+//                   is split into two sub-boxes at the widest gap);
 //                   larger boxes add their sums, and boxes wider than the
 //                   grid (points over all beat frequencies, or across its
 //                   periodic edge) each weight, to the grid with atomics
@@ -43,6 +45,7 @@
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -53,6 +56,7 @@ constexpr int kMaxCols = 1024;                        // widest box gathered per
 constexpr int kSlot = 1024;                           // tile cells kept per (block, channel)
 constexpr int kAccCells = 2048;                       // LDS accumulator cells of the column gather
 constexpr int kRowsReg = 16;                          // box rows held in registers by the column gather
+constexpr int kGapRows = 1024;                        // tallest box searched for a row gap to split at
 constexpr int kMaskBlocks = 1024;                     // blocks per coverage pass of a row
 constexpr int kSplit = 4;                             // threads per cell in the assembly
 constexpr int kAsmCols = 256 / kSplit;                // grid columns per assembly workgroup
@@ -70,8 +74,9 @@ struct nu_args {
     float beta;                 // kernel shape
     float2 *grid;               // [C][n2][n1]: weights of boxes that do not fit a tile slot
     float2 *rows;               // [C][n2][Ns]
-    float2 *tiles;              // [C][nblk][kSlot]: each block's box sums, row-major e1 x e2
-    int4 *desc;                 // [C][nblk]: box (lo1, lo2, e1, e2); e1 = 0 when not in a slot
+    float2 *tiles;              // [C][nblk][kSlot]: each block's (sub-)box sums, row-major e1 x e2
+    int4 *desc;                 // [C][nblk][2]: sub-boxes (lo1, lo2, e1 | e2 << 16, tile offset);
+                                //   e1 = 0 when not in a slot (the second one when unused)
     int *rowcov;                // [C][n2]: nonzero when some block wrote to the grid row
     int32_t nblk;               // pixel blocks
     const float *d1, *d2;       // deconvolution factors [Ns], [L]
@@ -155,6 +160,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     __shared__ __align__(16) float accbuf[2 * kAccCells];   // read as float4
     float *accr = accbuf, *acci = accbuf + kAccCells, *spw2r = accbuf;
     __shared__ int red[kSpreadThreads / 64];
+    __shared__ unsigned occ[kGapRows / 32];   // start rows occupied, for the split of tall boxes
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
     const int m = c / A.N, r = c % A.N;
@@ -199,22 +205,94 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
         lo2 = min(lo2, c2);
         hi2 = max(hi2, c2);
     }
+    int4 *dsc = A.desc + ((int64_t)c * A.nblk + blockIdx.x) * 2;
     lo1 = block_reduce(lo1, red, true);   // the barriers also publish the points
-    if (lo1 == INT_MAX) return;           // no pixel in this block (uniform)
+    if (lo1 == INT_MAX) {                 // no pixel in this block (uniform)
+        if (tid < 2) dsc[tid] = make_int4(0, 0, 0, 0);
+        return;
+    }
     hi1 = block_reduce(hi1, red, false);
     lo2 = block_reduce(lo2, red, true);
     hi2 = block_reduce(hi2, red, false);
     const int e1 = hi1 - lo1 + W, e2 = hi2 - lo2 + W;   // box of cells touched
     float2 *grid = A.grid + (int64_t)c * A.n2 * A.n1;
 
-    int4 *dsc = A.desc + (int64_t)c * A.nblk + blockIdx.x;
-    const bool slot = e1 * e2 <= kSlot && hi1 - lo1 < kMaxCols && e1 <= A.n1 && e2 <= A.n2;
-    if (tid == 0) *dsc = make_int4(lo1, lo2, slot ? e1 : 0, e2);
+    // ---- a box taller than the register rows whose window start rows fall
+    // into two groups apart (static and moving scatterers in one block) is
+    // split at the widest gap between occupied start rows, into two
+    // sub-boxes that each take the register gather below -------------------
+    int nsb = 1, split = 0;
+    int blo1[2] = {lo1, 0}, blo2[2] = {lo2, 0}, be1[2] = {e1, 0}, be2[2] = {e2, 0};
+    if (e2 > kRowsReg && hi2 - lo2 < kGapRows) {   // uniform
+        for (int w = tid; w < kGapRows / 32; w += kSpreadThreads) occ[w] = 0u;
+        __syncthreads();
+        for (int q = tid; q < npts; q += kSpreadThreads) {
+            const int rr = pm2[q] - lo2;
+            atomicOr(&occ[rr >> 5], 1u << (rr & 31));
+        }
+        __syncthreads();
+        // every run of occupied rows that ends at r < span - 1 is followed by
+        // a gap up to the next occupied row (row span - 1 is occupied); key:
+        // widest gap first, then lowest r
+        const int span = hi2 - lo2 + 1;
+        int best = -1;
+        for (int rr = tid; rr < span - 1; rr += kSpreadThreads) {
+            const bool run_end = (occ[rr >> 5] >> (rr & 31) & 1u) && !(occ[(rr + 1) >> 5] >> ((rr + 1) & 31) & 1u);
+            if (run_end) {
+                int wi = (rr + 2) >> 5;
+                unsigned bits = occ[wi] & (~0u << ((rr + 2) & 31));
+                while (!bits) bits = occ[++wi];
+                const int nx = wi * 32 + __builtin_ctz(bits);
+                best = max(best, (nx - rr) * kGapRows + (kGapRows - 1 - rr));
+            }
+        }
+        best = block_reduce(best, red, false);
+        if (best >= 0) {
+            const int gap = best / kGapRows, rsp = kGapRows - 1 - best % kGapRows;
+            const int e2a = rsp + W, e2b = (span - 1) - (rsp + gap) + W;
+            if (e2a <= kRowsReg && e2b <= kRowsReg && e2a <= A.n2 && e2b <= A.n2) {   // uniform
+                int alo = INT_MAX, ahi = INT_MIN, blo = INT_MAX, bhi = INT_MIN;
+                for (int q = tid; q < npts; q += kSpreadThreads) {
+                    if (pm2[q] - lo2 <= rsp) {
+                        alo = min(alo, pm1[q]);
+                        ahi = max(ahi, pm1[q]);
+                    } else {
+                        blo = min(blo, pm1[q]);
+                        bhi = max(bhi, pm1[q]);
+                    }
+                }
+                alo = block_reduce(alo, red, true);
+                ahi = block_reduce(ahi, red, false);
+                blo = block_reduce(blo, red, true);
+                bhi = block_reduce(bhi, red, false);
+                const int e1a = ahi - alo + W, e1b = bhi - blo + W;
+                if (e1a * e2a + e1b * e2b <= kSlot && (ahi - alo + 1) + (bhi - blo + 1) <= kMaxCols &&
+                    e1a + e1b <= kSpreadThreads && e1a <= A.n1 && e1b <= A.n1) {
+                    nsb = 2;
+                    split = rsp;
+                    blo1[0] = alo;
+                    blo1[1] = blo;
+                    blo2[1] = lo2 + rsp + gap;
+                    be1[0] = e1a;
+                    be1[1] = e1b;
+                    be2[0] = e2a;
+                    be2[1] = e2b;
+                }
+            }
+        }
+    }
+
+    const bool slot = nsb == 2 || (e1 * e2 <= kSlot && hi1 - lo1 < kMaxCols && e1 <= A.n1 && e2 <= A.n2);
+    if (tid == 0) {
+        dsc[0] = make_int4(blo1[0], blo2[0], slot ? be1[0] | be2[0] << 16 : 0, 0);
+        dsc[1] = make_int4(blo1[1], blo2[1], nsb == 2 ? be1[1] | be2[1] << 16 : 0, be1[0] * be2[0]);
+    }
     // flag the grid rows this block writes to (every row when the box is
     // taller than the grid): the FFT passes skip the rows no block touches
-    for (int t = tid; t < min(e2, A.n2); t += kSpreadThreads)
-        atomicOr(A.rowcov + (int64_t)c * A.n2 + pmod(lo2 + t, A.n2), 1);
-    if (hi1 - lo1 >= kMaxCols || e1 > A.n1 || e2 > A.n2) {
+    for (int sb = 0; sb < nsb; ++sb)
+        for (int t = tid; t < min(be2[sb], A.n2); t += kSpreadThreads)
+            atomicOr(A.rowcov + (int64_t)c * A.n2 + pmod(blo2[sb] + t, A.n2), 1);
+    if (nsb == 1 && (hi1 - lo1 >= kMaxCols || e1 > A.n1 || e2 > A.n2)) {
         // box wider than the grid or the column table: scatter each weight
         // to the grid (a lane per window cell, a wave per point)
         const int lane = tid & 63, wave = tid >> 6;
@@ -231,9 +309,19 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
         return;
     }
 
-    // ---- 2. sort by window column: key = (m1 - lo1) * kBlockPts + q --------
-    for (int q = tid; q < kBlockPts; q += kSpreadThreads)
-        key[q] = q < npts ? (pm1[q] - lo1) * kBlockPts + q : INT_MAX;
+    // ---- 2. sort by sub-box and window column: key = column * kBlockPts + q,
+    // the columns of the second sub-box numbered after those of the first ----
+    const int ncolA = be1[0] - W + 1;
+    const int ncol = ncolA + (nsb == 2 ? be1[1] - W + 1 : 0);
+    auto group = [&](int q) { return nsb == 2 && pm2[q] - lo2 > split ? 1 : 0; };
+    for (int q = tid; q < kBlockPts; q += kSpreadThreads) {
+        if (q < npts) {
+            const int g = group(q);
+            key[q] = ((g ? ncolA : 0) + pm1[q] - blo1[g]) * kBlockPts + q;
+        } else {
+            key[q] = INT_MAX;
+        }
+    }
     __syncthreads();
     for (int k = 2; k <= kBlockPts; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
@@ -251,12 +339,12 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
         }
     }
     // cs[k] = first sorted position whose column is >= k, k = 0 .. ncol;
-    // the records are copied into sorted order so that the gather reads them
-    // without an indirection
-    const int ncol = hi1 - lo1 + 1;
+    // the records (offsets from their sub-box's corner) are copied into
+    // sorted order so that the gather reads them without an indirection
     for (int s = tid; s < npts; s += kSpreadThreads) {
         const int q = key[s] % kBlockPts;
-        srec[s] = make_int2((pm1[q] - lo1) | ((pm2[q] - lo2) << 16), q);
+        const int g = group(q);
+        srec[s] = make_int2((pm1[q] - blo1[g]) | ((pm2[q] - blo2[g]) << 16), q);
         spc[s] = pc[q];
         const int col = key[s] / kBlockPts;
         const int prev = s == 0 ? -1 : key[s - 1] / kBlockPts;
@@ -272,25 +360,41 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     // order per cell ---------------------------------------------------------
     const int E = e1 * e2;
     const int nparts = slot ? min(kSpreadThreads / e1, kAccCells / E) : 0;
-    if (nparts > 0 && e2 <= kRowsReg) {
-        // boxes of at most 16 rows: the row sums of a column live in
-        // registers, and each point's w2 is laid out at its row offset once
-        // per block so that a candidate costs four LDS vector reads and 32 FMAs
+    // (Sub-)boxes of at most 16 rows: the row sums of a column live in
+    // registers, and each point's w2 is laid out at its row offset once per
+    // block so that a candidate costs four LDS vector reads and 32 FMAs.  TWO
+    // (two sub-boxes) is a compile-time flag, so that the one-box case keeps
+    // its simple indexing.
+    auto register_gather = [&](auto two_t) {
+        constexpr bool TWO = decltype(two_t)::value;
         for (int k = tid; k < npts * kRowsReg; k += kSpreadThreads) {
             const int s = k / kRowsReg, rr = k % kRowsReg;
             const int2 rec = srec[s];
             const int d = rr - (rec.x >> 16);
             spw2r[k] = d >= 0 && d < W ? pw2[rec.y * W + d] : 0.f;
         }
+        // threads, shares and accumulator cells of the sub-boxes: the first
+        // takes threads in proportion to its points (at least a column's
+        // worth each), its shares leave room for one of the second
+        const int EA = be1[0] * be2[0], EB = TWO ? be1[1] * be2[1] : 0;
+        const int nA = TWO ? cs[ncolA] : npts;   // points of the first sub-box
+        const int tA = TWO ? min(max(kSpreadThreads * nA / npts, be1[0]), kSpreadThreads - be1[1]) : kSpreadThreads;
+        const int pA = min(tA / be1[0], (kAccCells - EB) / EA);
+        const int pB = TWO ? min((kSpreadThreads - tA) / be1[1], (kAccCells - pA * EA) / EB) : 0;
         __syncthreads();
-        const int x = tid % e1, p = tid / e1;
+        const int g = TWO && tid >= tA ? 1 : 0;
+        const int tl = g ? tid - tA : tid;
+        const int ex = g ? be1[1] : be1[0], ey = g ? be2[1] : be2[0];
+        const int x = tl % ex, p = tl / ex;
+        const int np = g ? pB : pA;
+        const int coff = g ? ncolA : 0, ncg = g ? ncol - ncolA : ncolA;
         float ar[kRowsReg], ai[kRowsReg];
 #pragma unroll
         for (int r = 0; r < kRowsReg; ++r) ar[r] = ai[r] = 0.f;
-        if (p < nparts) {
-            const int k0 = max(0, x - W + 1), k1 = min(x, ncol - 1);
-            const int sb = cs[k0], len = cs[k1 + 1] - sb;
-            const int s_beg = sb + len * p / nparts, s_end = sb + len * (p + 1) / nparts;
+        if (p < np) {
+            const int k0 = max(0, x - W + 1), k1 = min(x, ncg - 1);
+            const int sb = cs[coff + k0], len = cs[coff + k1 + 1] - sb;
+            const int s_beg = sb + len * p / np, s_end = sb + len * (p + 1) / np;
             for (int s = s_beg; s < s_end; ++s) {
                 const int2 rec = srec[s];
                 const float2 cv = spc[s];
@@ -312,25 +416,36 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
             }
         }
         __syncthreads();   // spw2r is overwritten by the accumulators below
-        if (p < nparts) {
+        if (p < np) {
+            const int ab = g ? pA * EA + p * EB : p * EA;
 #pragma unroll
             for (int r = 0; r < kRowsReg; ++r) {
-                if (r < e2) {
-                    accr[p * E + r * e1 + x] = ar[r];
-                    acci[p * E + r * e1 + x] = ai[r];
+                if (r < ey) {
+                    accr[ab + r * ex + x] = ar[r];
+                    acci[ab + r * ex + x] = ai[r];
                 }
             }
         }
         __syncthreads();
+        // the slot holds the first sub-box's cells, then the second's
         float2 *slotp = A.tiles + ((int64_t)c * A.nblk + blockIdx.x) * kSlot;
-        for (int cell = tid; cell < E; cell += kSpreadThreads) {
+        for (int cell = tid; cell < EA + EB; cell += kSpreadThreads) {
+            const bool inB = TWO && cell >= EA;
+            const int base = inB ? pA * EA + (cell - EA) : cell, stride = inB ? EB : EA, n = inB ? pB : pA;
             float sr = 0.f, si = 0.f;
-            for (int q = 0; q < nparts; ++q) {
-                sr += accr[q * E + cell];
-                si += acci[q * E + cell];
+            for (int q = 0; q < n; ++q) {
+                sr += accr[base + q * stride];
+                si += acci[base + q * stride];
             }
             slotp[cell] = make_float2(sr, si);   // the assembly adds the slot to the grid rows it covers
         }
+    };
+    if (nsb == 2) {
+        register_gather(std::true_type{});
+        return;
+    }
+    if (nparts > 0 && e2 <= kRowsReg) {
+        register_gather(std::false_type{});
         return;
     }
     if (nparts > 0) {
@@ -421,10 +536,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
 }
 
 // Adds the tile slots to the grid: a workgroup per (channel, 8 grid rows n2/8
-// apart, 64 columns), four threads per cell.  The blocks whose box covers the
-// row and overlaps the workgroup's columns are listed in LDS in block order
-// (a coverage bitmask, set in any order, read in order), and every cell sums
-// its tiles in that order, so the result does not depend on scheduling.
+// apart, 64 columns), four threads per cell.  The (sub-)boxes that cover the
+// row and overlap the workgroup's columns are listed in LDS in block order
+// (a coverage bitmask over the two descriptor entries of every block, set in
+// any order, read in order), and every cell sums its tiles in that order, so
+// the result does not depend on scheduling.
 // Rows no block wrote to (their flag, set by the spreading kernel, is zero)
 // are skipped.
 __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
@@ -432,8 +548,8 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
     constexpr int kWords = kMaskBlocks / 32;
     __shared__ unsigned mask[kWords];
     __shared__ int woff[kWords];
-    __shared__ int4 ldesc[kMaskBlocks];   // descriptors of the covering blocks, in block order
-    __shared__ int lid[kMaskBlocks];
+    __shared__ int4 ldesc[kMaskBlocks];   // descriptors of the covering sub-boxes, in block order
+    __shared__ int lid[kMaskBlocks];      // their entries: 2 block + sub-box
     __shared__ int ncov;
     __shared__ float2 part[kSplit][kAsmCols];
     const int c = blockIdx.z;
@@ -442,15 +558,16 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
     const int lc = threadIdx.x % kAsmCols, sp = threadIdx.x / kAsmCols;
     const int c0 = blockIdx.x * kAsmCols;
     const int col = c0 + lc;
-    const int4 *dc = A.desc + (int64_t)c * A.nblk;
+    const int4 *dc = A.desc + (int64_t)c * A.nblk * 2;
     const float2 *tc = A.tiles + (int64_t)c * A.nblk * kSlot;
+    const int nent = 2 * A.nblk;
     // rows blockIdx.y + k gridDim.y: the covered rows, which lie together
     // around the scene's Doppler band, go to different workgroups
     for (int m2 = blockIdx.y; m2 < A.n2; m2 += gridDim.y) {
         if (rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) == 0) continue;   // no block wrote to this row (uniform)
         float2 acc = make_float2(0.f, 0.f);
-        for (int b0 = 0; b0 < A.nblk; b0 += kMaskBlocks) {
-            const int nb = min(kMaskBlocks, A.nblk - b0);
+        for (int b0 = 0; b0 < nent; b0 += kMaskBlocks) {
+            const int nb = min(kMaskBlocks, nent - b0);
             const int nw = (nb + 31) / 32;
             for (int w = threadIdx.x; w < nw; w += blockDim.x) mask[w] = 0u;
             __syncthreads();
@@ -458,8 +575,8 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
                 const int4 d = dc[b0 + b];
                 // the box covers this row and overlaps this workgroup's columns
                 // c0 .. c0 + kAsmCols - 1 (both taken around the periodic grid)
-                if (d.z > 0 && pmod(m2 - d.y, A.n2) < d.w &&
-                    (pmod(c0 - d.x, A.n1) < d.z || pmod(d.x - c0, A.n1) < kAsmCols))
+                if (d.z > 0 && pmod(m2 - d.y, A.n2) < (d.z >> 16) &&
+                    (pmod(c0 - d.x, A.n1) < (d.z & 0xffff) || pmod(d.x - c0, A.n1) < kAsmCols))
                     atomicOr(&mask[b >> 5], 1u << (b & 31));
             }
             __syncthreads();
@@ -488,7 +605,7 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
                 __syncthreads();
                 if (col < A.n1) {
                     const int kb = (int)((int64_t)nc * sp / kSplit), ke = (int)((int64_t)nc * (sp + 1) / kSplit);
-                    // kU covering blocks per round: their tile loads are in flight together
+                    // kU covering sub-boxes per round: their tile loads are in flight together
                     constexpr int kU = 8;
                     for (int k0 = kb; k0 < ke; k0 += kU) {
                         float2 t[kU];
@@ -497,10 +614,10 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
                             t[u] = make_float2(0.f, 0.f);
                             if (k0 + u < ke) {
                                 const int4 d = ldesc[k0 + u];
-                                const int xx = pmod(col - d.x, A.n1);
-                                if (xx < d.z)
-                                    t[u] = rs_gload2(tc + (int64_t)lid[k0 + u] * kSlot,
-                                                     pmod(m2 - d.y, A.n2) * d.z + xx);
+                                const int xx = pmod(col - d.x, A.n1), ex = d.z & 0xffff;
+                                if (xx < ex)
+                                    t[u] = rs_gload2(tc + (int64_t)(lid[k0 + u] >> 1) * kSlot + d.w,
+                                                     pmod(m2 - d.y, A.n2) * ex + xx);
                             }
                         }
 #pragma unroll
@@ -695,7 +812,7 @@ size_t rs_nufft_workspace(const rs_plan *pl, int64_t P)
     const int64_t nblk = (P + kBlockPts - 1) / kBlockPts;
     return up((size_t)pl->C * pl->nu_n1 * pl->nu_n2 * 8) + up((size_t)pl->C * pl->nu_n2 * 4) +
            up((size_t)pl->C * pl->nu_n2 * pl->Ns * 8) + up((size_t)pl->C * nblk * kSlot * 8) +
-           up((size_t)pl->C * nblk * sizeof(int4));
+           up((size_t)pl->C * nblk * 2 * sizeof(int4));
 }
 
 rs_status rs_nufft_enqueue(const rs_plan *pl, const rs_pixels *px, void *cube, void *ws, hipStream_t st)

@@ -100,6 +100,13 @@ def test_plan_describe_and_workspace():
     # partial sums of every chunk + one scale exponent per chunk (256-byte padded)
     scale_bytes = (d["chunks"] * 4 + 255) // 256 * 256
     assert plan.workspace_bytes(px.P) == d["chunks"] * 12 * 128 * 256 * 8 + scale_bytes
+    # a pixel count whose chunks would exceed 2^30 pixels is refused, not wrapped
+    big = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=1 << 40)
+    with pytest.raises(rs.RSError) as e:
+        big.workspace_bytes(1 << 40)
+    assert e.value.status == rs.RS_E_INVALID
+    big.close()
+    plan.close()
 
 
 def test_ws_variant_equals_allocating_variant():

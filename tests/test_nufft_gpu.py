@@ -162,3 +162,69 @@ def test_more_blocks_than_one_coverage_pass():
     rel, _ = errors(got, oracle.cube(r, px))
     print(f"nufft 600k pixels: vs NUFFT oracle {rel_nu:.2e}, vs exact {rel:.2e}", flush=True)
     assert rel_nu <= GATE_FP32 and rel <= 1e-6 + GATE_FP32
+
+
+def _two_group_scene(r, P, seed):
+    """Pixels whose blocks of 256 each hold static scatterers (v = 0) and
+    moving ones in a narrow Doppler band a quarter cycle away, ranges rising
+    slowly with the index (as along an image row): every block's box is
+    tall, and its start rows fall into two groups a wide gap apart."""
+    rng = np.random.default_rng(seed)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    Kd = 2 * r.fc * r.Tb / r.c0                       # cycles per block per (m/s)
+    rr = 1.0 + 5.0 * np.arange(P) / P + rng.uniform(0, 0.02, P)
+    az = rng.uniform(-0.5, 0.5, P)
+    v = np.where(np.arange(P) % 2 == 0, 0.0, (0.25 + 30.0) / Kd + rng.uniform(-2e-4, 2e-4, P))
+    return scenes.Pixels(f32(rr * np.sin(az)), f32(rr * np.cos(az)), f32(rng.uniform(-0.3, 0.3, P)),
+                         f32(rng.lognormal(0, 0.5, P)), f32(v))
+
+
+def _split_blocks(r, px, tol):
+    """Blocks (of channel 0) whose box is taller than 16 rows and whose start
+    rows split at the widest gap into two groups of at most 16 rows each."""
+    w, _ = onufft.es_params(tol)
+    n2 = onufft.fine_size(r.L, w)
+    _, _, beta = oracle.default().chan_args(r, px, 0)
+    v = -beta - np.rint(-beta)
+    m2 = np.ceil(v * n2 - w / 2.0).astype(np.int64)
+    count = 0
+    for b0 in range(0, px.P, 256):
+        rows = np.unique(m2[b0:b0 + 256])
+        if rows[-1] - rows[0] + w <= 16:
+            continue
+        k = int(np.argmax(np.diff(rows)))
+        if rows[k] - rows[0] + w <= 16 and rows[-1] - rows[k + 1] + w <= 16:
+            count += 1
+    return count, (px.P + 255) // 256
+
+
+@pytest.mark.parametrize("name", ["ragged", "frame_shape"])
+@pytest.mark.parametrize("tol", [1e-2, 1e-6])
+def test_blocks_split_into_two_sub_boxes(name, tol):
+    """Blocks mixing static and moving scatterers: their tall boxes are split
+    into two sub-boxes; the cube still matches the NUFFT oracle and the exact
+    sum, and a second run gives the same bits."""
+    r = RADARS[name]()
+    px = _two_group_scene(r, 2048 + 77, seed=470)
+    split, nblk = _split_blocks(r, px, tol)
+    assert split == nblk, (split, nblk)              # the scene exercises the split in every block
+    got = _synth(r, px, tol)
+    again = _synth(r, px, tol)
+    rel_nu, _ = errors(got, onufft.nufft_cube(r, px, tol))
+    rel, _ = errors(got, oracle.cube(r, px))
+    print(f"nufft two groups {name} tol={tol:g}: vs NUFFT oracle {rel_nu:.2e}, vs exact {rel:.2e}", flush=True)
+    assert np.array_equal(got, again)
+    assert rel_nu <= GATE_FP32 and rel <= tol + GATE_FP32
+
+
+def test_largest_serving_request_sampled():
+    """The largest serving-size request (12 x 16 channels, N_s 512, 234,256
+    pixels; a quarter of its blocks take the two-sub-box split) at tolerance
+    1e-6: sampled entries against the exact sum."""
+    big = max((q for q in scenes.serving_requests(48) if q.radar.C == 192),
+              key=lambda q: q.pixels.P * q.radar.Ns * q.radar.L)
+    got = _synth(big.radar, big.pixels, 1e-6)
+    c, l, n = sample_indices(big.radar.cube_shape(), 128, seed=13)
+    rel, mx = errors(got[c, l, n], oracle.entries(big.radar, big.pixels, c, l, n))
+    print(f"nufft largest request: relL2 {rel:.2e} maxabs {mx:.2e}", flush=True)
+    assert rel <= 1e-6 + GATE_FP32
