@@ -52,7 +52,7 @@ namespace {
 
 constexpr int kSpreadThreads = 256;
 constexpr int kBlockPts = 256;                        // pixels per spreading workgroup (power of two)
-constexpr int kMaxCols = 1024;                        // widest box gathered per cell
+constexpr int kMaxCols = 512;                         // widest box gathered per cell
 constexpr int kSlot = 1024;                           // tile cells kept per (block, channel)
 constexpr int kAccCells = 2048;                       // LDS accumulator cells of the column gather
 constexpr int kRowsReg = 16;                          // box rows held in registers by the column gather
@@ -135,32 +135,39 @@ __device__ __forceinline__ int block_reduce(int v, int *red, bool is_min)
 // Spreading of one pixel block onto one channel's grid, gathered per cell.
 //   1. A thread per pixel evaluates its point into LDS: the first cells
 //      (m1, m2) of its W x W window, its strength c and the 2 W kernel
-//      weights; the block's bounding box of cells follows by reduction.
-//   2. The points are sorted by window column (bitonic sort of
-//      (m1 - lo1, index) keys, so the order is fixed), and cs[k] marks where
+//      weights; the block's bounding box of cells follows by reduction (and
+//      a tall box of two row groups is split into two sub-boxes).
+//   2. The points are sorted by (sub-box, window column, index) -- a rank
+//      sort of unique keys, so the order is fixed -- and cs[k] marks where
 //      column k starts.
-//   3. A thread per box cell (x, y) sums, in registers, c w1[x - m1]
-//      w2[y - m2] over the points whose window covers it -- those with
-//      m1 - lo1 in [x - W + 1, x], a contiguous run of the sorted order --
-//      and adds the sum to the grid cell with one global atomic per part.
+//   3. A thread per box column (and share of its candidates) sums, in
+//      registers, c w1[x - m1] w2[y - m2] over the points whose window
+//      covers it -- those with m1 - lo1 in [x - W + 1, x], a contiguous run
+//      of the sorted order -- and the shares are added in a fixed order into
+//      the block's tile slot; boxes that fit no slot add to the grid with
+//      global atomics.
 // No LDS atomics: neighbouring pixels share most of their window, and
 // atomics on the same LDS cells from successive instructions serialise.
+// Under 40 KB of LDS for W <= 7 and under 128 VGPRs: four workgroups per CU.
 template <int W>
 __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
 {
     __shared__ int pm1[kBlockPts], pm2[kBlockPts];
-    __shared__ float2 pc[kBlockPts];
     __shared__ float pw1[kBlockPts * W], pw2[kBlockPts * W];
-    __shared__ int key[kBlockPts];
     __shared__ int cs[kMaxCols + 1];
     __shared__ int2 srec[kBlockPts];      // sorted: ((m1 - lo1) | (m2 - lo2) << 16, point index)
     __shared__ float2 spc[kBlockPts];     // sorted strengths
     // per-share accumulators [share][row][column]; before them, in the same
-    // space, each sorted point's w2 placed at its row of the box (16 rows)
+    // space, each sorted point's w2 placed at its row of the box (16 rows).
+    // Until the sorted records are complete the space holds the points'
+    // strengths, the sort keys and the start-row occupancy of the split.
     __shared__ __align__(16) float accbuf[2 * kAccCells];   // read as float4
     float *accr = accbuf, *acci = accbuf + kAccCells, *spw2r = accbuf;
+    float2 *pc = reinterpret_cast<float2 *>(accbuf);                          // [kBlockPts]
+    int *key = reinterpret_cast<int *>(accbuf + 2 * kBlockPts);               // [kBlockPts], read as int4
+    unsigned *occ = reinterpret_cast<unsigned *>(accbuf + 3 * kBlockPts);     // [kGapRows / 32]
+    static_assert(3 * kBlockPts + kGapRows / 32 <= 2 * kAccCells, "aliases fit the accumulator space");
     __shared__ int red[kSpreadThreads / 64];
-    __shared__ unsigned occ[kGapRows / 32];   // start rows occupied, for the split of tall boxes
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
     const int m = c / A.N, r = c % A.N;
@@ -310,7 +317,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     }
 
     // ---- 2. sort by sub-box and window column: key = column * kBlockPts + q,
-    // the columns of the second sub-box numbered after those of the first ----
+    // the columns of the second sub-box numbered after those of the first;
+    // a rank sort (no barriers inside) ----------------------------------------
     const int ncolA = be1[0] - W + 1;
     const int ncol = ncolA + (nsb == 2 ? be1[1] - W + 1 : 0);
     auto group = [&](int q) { return nsb == 2 && pm2[q] - lo2 > split ? 1 : 0; };
@@ -323,31 +331,34 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
         }
     }
     __syncthreads();
-    for (int k = 2; k <= kBlockPts; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int t = tid; t < kBlockPts / 2; t += kSpreadThreads) {
-                const int i0 = 2 * t - (t & (jj - 1));
-                const int i1 = i0 + jj;
-                const int a = key[i0], bb = key[i1];
-                const bool up = (i0 & k) == 0;
-                if ((a > bb) == up) {
-                    key[i0] = bb;
-                    key[i1] = a;
-                }
-            }
-            __syncthreads();
+    // the sorted position of a point is the number of smaller keys (the keys
+    // are unique, so the ranks are a permutation); every lane of a wave
+    // reads the same keys at once, which the LDS broadcasts.  The records
+    // (offsets from their sub-box's corner) are stored in sorted order so
+    // that the gather reads them without an indirection.
+    static_assert(kSpreadThreads == kBlockPts, "one point per thread");
+    if (tid < npts) {
+        const int k = key[tid];
+        const int4 *k4 = reinterpret_cast<const int4 *>(key);
+        int rank = 0;
+#pragma unroll 4
+        for (int i = 0; i < kBlockPts / 4; ++i) {
+            const int4 v = k4[i];
+            rank += (v.x < k) + (v.y < k) + (v.z < k) + (v.w < k);
         }
+        const int g = group(tid);
+        srec[rank] = make_int2((pm1[tid] - blo1[g]) | ((pm2[tid] - blo2[g]) << 16), tid);
+        spc[rank] = pc[tid];
     }
-    // cs[k] = first sorted position whose column is >= k, k = 0 .. ncol;
-    // the records (offsets from their sub-box's corner) are copied into
-    // sorted order so that the gather reads them without an indirection
+    __syncthreads();
+    // cs[k] = first sorted position whose column is >= k, k = 0 .. ncol
+    auto column = [&](int s) {
+        const int2 rec = srec[s];
+        return (group(rec.y) ? ncolA : 0) + (rec.x & 0xffff);
+    };
     for (int s = tid; s < npts; s += kSpreadThreads) {
-        const int q = key[s] % kBlockPts;
-        const int g = group(q);
-        srec[s] = make_int2((pm1[q] - blo1[g]) | ((pm2[q] - blo2[g]) << 16), q);
-        spc[s] = pc[q];
-        const int col = key[s] / kBlockPts;
-        const int prev = s == 0 ? -1 : key[s - 1] / kBlockPts;
+        const int col = column(s);
+        const int prev = s == 0 ? -1 : column(s - 1);
         for (int k = prev + 1; k <= col; ++k) cs[k] = s;
         if (s == npts - 1)
             for (int k = col + 1; k <= ncol; ++k) cs[k] = npts;
