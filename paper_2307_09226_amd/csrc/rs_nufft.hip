@@ -557,6 +557,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
 __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
 {
     constexpr int kWords = kMaskBlocks / 32;
+    static_assert(kWords <= 64 && kMaskBlocks % kFftThreads == 0, "one wave scans the words; whole entries per thread");
     __shared__ unsigned mask[kWords];
     __shared__ int woff[kWords];
     __shared__ int4 ldesc[kMaskBlocks];   // descriptors of the covering sub-boxes, in block order
@@ -572,45 +573,71 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
     const int4 *dc = A.desc + (int64_t)c * A.nblk * 2;
     const float2 *tc = A.tiles + (int64_t)c * A.nblk * kSlot;
     const int nent = 2 * A.nblk;
-    // rows blockIdx.y + k gridDim.y: the covered rows, which lie together
-    // around the scene's Doppler band, go to different workgroups
-    for (int m2 = blockIdx.y; m2 < A.n2; m2 += gridDim.y) {
-        if (rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) == 0) continue;   // no block wrote to this row (uniform)
+    // rows blockIdx.y + k gridDim.y (k < kAsmRows): the covered rows, which
+    // lie together around the scene's Doppler band, go to different
+    // workgroups.  Their flags are read at once; rows no block wrote to are
+    // skipped.
+    __shared__ unsigned rows_live;
+    if (threadIdx.x < 64) {
+        const int m2 = blockIdx.y + threadIdx.x * gridDim.y;
+        const bool live = (int)threadIdx.x < kAsmRows && m2 < A.n2 && rs_gload(A.rowcov, (int64_t)c * A.n2 + m2) != 0;
+        const unsigned long long bal = __ballot(live);
+        if (threadIdx.x == 0) rows_live = (unsigned)bal;
+    }
+    __syncthreads();
+    for (unsigned live = rows_live; live; live &= live - 1u) {
+        const int m2 = blockIdx.y + __builtin_ctz(live) * gridDim.y;
         float2 acc = make_float2(0.f, 0.f);
         for (int b0 = 0; b0 < nent; b0 += kMaskBlocks) {
             const int nb = min(kMaskBlocks, nent - b0);
             const int nw = (nb + 31) / 32;
             for (int w = threadIdx.x; w < nw; w += blockDim.x) mask[w] = 0u;
             __syncthreads();
-            for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-                const int4 d = dc[b0 + b];
-                // the box covers this row and overlaps this workgroup's columns
-                // c0 .. c0 + kAsmCols - 1 (both taken around the periodic grid)
-                if (d.z > 0 && pmod(m2 - d.y, A.n2) < (d.z >> 16) &&
-                    (pmod(c0 - d.x, A.n1) < (d.z & 0xffff) || pmod(d.x - c0, A.n1) < kAsmCols))
-                    atomicOr(&mask[b >> 5], 1u << (b & 31));
+            // entries b = threadIdx.x + kFftThreads i: their descriptors stay in
+            // registers until they are placed in the list
+            constexpr int kPer = kMaskBlocks / kFftThreads;
+            int4 dv[kPer];
+            bool hit[kPer];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int b = threadIdx.x + kFftThreads * i;
+                hit[i] = false;
+                if (b < nb) {
+                    dv[i] = dc[b0 + b];
+                    const int4 d = dv[i];
+                    // the box covers this row and overlaps this workgroup's columns
+                    // c0 .. c0 + kAsmCols - 1 (both taken around the periodic grid)
+                    hit[i] = d.z > 0 && pmod(m2 - d.y, A.n2) < (d.z >> 16) &&
+                             (pmod(c0 - d.x, A.n1) < (d.z & 0xffff) || pmod(d.x - c0, A.n1) < kAsmCols);
+                    if (hit[i]) atomicOr(&mask[b >> 5], 1u << (b & 31));
+                }
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
-                int o = 0;
-                for (int w = 0; w < nw; ++w) {
-                    woff[w] = o;
-                    o += __builtin_popcount(mask[w]);
+            // word offsets: an inclusive scan of the words' bit counts over the
+            // first wave (kWords <= 64)
+            if (threadIdx.x < 64) {
+                const int cnt = (int)threadIdx.x < nw ? __builtin_popcount(mask[threadIdx.x]) : 0;
+                int incl = cnt;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const int v = __shfl_up(incl, off);
+                    if ((int)threadIdx.x >= off) incl += v;
                 }
-                ncov = o;
+                if ((int)threadIdx.x < nw) woff[threadIdx.x] = incl - cnt;
+                if (threadIdx.x == 63) ncov = incl;
             }
             __syncthreads();
             const int nc = ncov;
             if (nc > 0) {
-                for (int w = threadIdx.x; w < nw; w += blockDim.x) {
-                    unsigned bits = mask[w];
-                    int o = woff[w];
-                    while (bits) {
-                        const int b = b0 + w * 32 + __builtin_ctz(bits);
-                        bits &= bits - 1u;
-                        lid[o] = b;
-                        ldesc[o] = dc[b];
-                        ++o;
+                // each covering entry goes to its place in block order
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    if (hit[i]) {
+                        const int b = threadIdx.x + kFftThreads * i;
+                        const int w = b >> 5;
+                        const int o = woff[w] + __builtin_popcount(mask[w] & ((1u << (b & 31)) - 1u));
+                        lid[o] = b0 + b;
+                        ldesc[o] = dv[i];
                     }
                 }
                 __syncthreads();
