@@ -271,6 +271,14 @@ static rs_status plan_common(const rs_radar *r, rs_form form, rs_dtype dtype, in
         if ((int64_t)r->M * r->N > 65535) return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves <= 65535 channels");
         if (max_pixels > ((int64_t)1 << 31) - 1)
             return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves max_pixels < 2^31");
+        // its FFT passes launch up to one workgroup of 256 per grid row and
+        // per fast-time sample and channel: both counts stay below 2^24
+        int w = 0;
+        double beta = 0.0;
+        rs_nufft_params(tol, &w, &beta);
+        const int64_t C = (int64_t)r->M * r->N;
+        if (C * rs_nufft_fine(r->L, w) >= ((int64_t)1 << 24) || C * r->Ns >= ((int64_t)1 << 24))
+            return rs_fail(RS_E_UNSUPPORTED, "the NUFFT form serves channels x grid rows and channels x Ns below 2^24");
     }
 
     rs_plan *pl = new (std::nothrow) rs_plan();

@@ -99,6 +99,12 @@ def test_nufft_plan_arguments_rejected_on_host():
         assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st2), 0, 10, 1e-6, ctypes.byref(h)) == code, kw
         assert rs.lib.rs_cube_plan(ctypes.byref(st2), rs.RS_FORM_NUFFT, 0, 10, ctypes.byref(h)) == code, kw
     assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st), 0, 1 << 31, 1e-6, ctypes.byref(h)) == rs.RS_E_UNSUPPORTED
+    # 16,384 channels: 2^25 grid rows (L 1024, grid 2048) or 2^24 fast-time
+    # samples (Ns 1024) over all channels are refused before any device call
+    for Ns, L, code in ((64, 1024, rs.RS_E_UNSUPPORTED), (1024, 64, rs.RS_E_UNSUPPORTED)):
+        st3, keep3 = rs._radar_struct(scenes.radar_for(128, 128, Ns, L, Fs=10e6, Tb=120e-6))
+        assert rs.lib.rs_cube_plan_nufft(ctypes.byref(st3), 0, 10, 1e-6, ctypes.byref(h)) == code, (Ns, L)
+        assert "2^24" in rs.rs_last_error()
 
 
 def test_tune_arguments_rejected_on_host():
