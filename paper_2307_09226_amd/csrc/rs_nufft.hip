@@ -58,8 +58,7 @@ constexpr int kAccCells = 2048;                       // LDS accumulator cells o
 constexpr int kRowsReg = 16;                          // box rows held in registers by the column gather
 constexpr int kGapRows = 1024;                        // tallest box searched for a row gap to split at
 constexpr int kMaskBlocks = 1024;                     // blocks per coverage pass of a row
-constexpr int kSplit = 4;                             // threads per cell in the assembly
-constexpr int kAsmCols = 256 / kSplit;                // grid columns per assembly workgroup
+constexpr int kAsmGroups = 8192;                      // assembly workgroups enough for 256 columns each
 constexpr int kAsmRows = 8;                           // grid rows per assembly workgroup
 constexpr int kFftThreads = 256;
 constexpr int kFftElems = 4096;                       // complex values per FFT workgroup
@@ -547,15 +546,20 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
 }
 
 // Adds the tile slots to the grid: a workgroup per (channel, 8 grid rows n2/8
-// apart, 64 columns), four threads per cell.  The (sub-)boxes that cover the
+// apart, 256 / SPLIT columns), SPLIT threads per cell (SPLIT = 4 where the
+// launch is small, so that more workgroups share it; 1 where channels are
+// many, so that fewer column groups repeat the scan of the descriptors).
+// The (sub-)boxes that cover the
 // row and overlap the workgroup's columns are listed in LDS in block order
 // (a coverage bitmask over the two descriptor entries of every block, set in
 // any order, read in order), and every cell sums its tiles in that order, so
 // the result does not depend on scheduling.
 // Rows no block wrote to (their flag, set by the spreading kernel, is zero)
 // are skipped.
+template <int SPLIT>
 __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
 {
+    constexpr int kSplit = SPLIT, kAsmCols = kFftThreads / SPLIT;
     constexpr int kWords = kMaskBlocks / 32;
     static_assert(kWords <= 64 && kMaskBlocks % kFftThreads == 0, "one wave scans the words; whole entries per thread");
     __shared__ unsigned mask[kWords];
@@ -565,7 +569,7 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_assemble(nu_args A)
     __shared__ int ncov;
     __shared__ float2 part[kSplit][kAsmCols];
     const int c = blockIdx.z;
-    // thread = (column, quarter of the covering list): the four partial sums
+    // thread = (column, share of the covering list): the SPLIT partial sums
     // of a cell are added in a fixed order at the end
     const int lc = threadIdx.x % kAsmCols, sp = threadIdx.x / kAsmCols;
     const int c0 = blockIdx.x * kAsmCols;
@@ -908,10 +912,19 @@ rs_status rs_nufft_enqueue(const rs_plan *pl, const rs_pixels *px, void *cube, v
         default: return rs_fail(RS_E_UNSUPPORTED, "NUFFT kernel width %d not built", pl->nu_w);
         }
     }
-    if (A.nblk > 0)
-        hipLaunchKernelGGL(k_nufft_assemble, dim3((unsigned)((pl->nu_n1 + kAsmCols - 1) / kAsmCols),
-                                                  (unsigned)std::max(1, pl->nu_n2 / kAsmRows), (unsigned)pl->C),
-                           dim3(kFftThreads), 0, st, A);
+    if (A.nblk > 0) {
+        const int gy = std::max(1, pl->nu_n2 / kAsmRows);
+        const int64_t wide = (int64_t)((pl->nu_n1 + kFftThreads - 1) / kFftThreads) * gy * pl->C;
+        if (wide >= kAsmGroups)
+            hipLaunchKernelGGL(k_nufft_assemble<1>, dim3((unsigned)((pl->nu_n1 + kFftThreads - 1) / kFftThreads),
+                                                         (unsigned)gy, (unsigned)pl->C),
+                               dim3(kFftThreads), 0, st, A);
+        else
+            hipLaunchKernelGGL(k_nufft_assemble<4>,
+                               dim3((unsigned)((pl->nu_n1 + kFftThreads / 4 - 1) / (kFftThreads / 4)), (unsigned)gy,
+                                    (unsigned)pl->C),
+                               dim3(kFftThreads), 0, st, A);
+    }
     const int logn1 = log2i(pl->nu_n1), logn2 = log2i(pl->nu_n2);
     // few rows or columns per workgroup: only the rows some block wrote to
     // carry work, and each pass then takes about one workgroup's time
