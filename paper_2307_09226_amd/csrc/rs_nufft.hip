@@ -131,6 +131,29 @@ __device__ __forceinline__ int block_reduce(int v, int *red, bool is_min)
     return r;
 }
 
+// Block-wide component-wise minimum of v; every thread gets it (a maximum
+// is taken as the minimum of ~x, which is order-reversing and cannot
+// overflow).
+__device__ __forceinline__ int4 block_min4(int4 v, int4 *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x = min(v.x, __shfl_xor(v.x, o));
+        v.y = min(v.y, __shfl_xor(v.y, o));
+        v.z = min(v.z, __shfl_xor(v.z, o));
+        v.w = min(v.w, __shfl_xor(v.w, o));
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int4 r = red[0];
+    for (int i = 1; i < kSpreadThreads / 64; ++i) {
+        const int4 t = red[i];
+        r = make_int4(min(r.x, t.x), min(r.y, t.y), min(r.z, t.z), min(r.w, t.w));
+    }
+    __syncthreads();
+    return r;
+}
+
 // Spreading of one pixel block onto one channel's grid, gathered per cell.
 //   1. A thread per pixel evaluates its point into LDS: the first cells
 //      (m1, m2) of its W x W window, its strength c and the 2 W kernel
@@ -167,6 +190,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     unsigned *occ = reinterpret_cast<unsigned *>(accbuf + 3 * kBlockPts);     // [kGapRows / 32]
     static_assert(3 * kBlockPts + kGapRows / 32 <= 2 * kAccCells, "aliases fit the accumulator space");
     __shared__ int red[kSpreadThreads / 64];
+    __shared__ int4 red4[kSpreadThreads / 64];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
     const int m = c / A.N, r = c % A.N;
@@ -212,14 +236,17 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
         hi2 = max(hi2, c2);
     }
     int4 *dsc = A.desc + ((int64_t)c * A.nblk + blockIdx.x) * 2;
-    lo1 = block_reduce(lo1, red, true);   // the barriers also publish the points
+    {   // the barriers also publish the points
+        const int4 b = block_min4(make_int4(lo1, ~hi1, lo2, ~hi2), red4);
+        lo1 = b.x;
+        hi1 = ~b.y;
+        lo2 = b.z;
+        hi2 = ~b.w;
+    }
     if (lo1 == INT_MAX) {                 // no pixel in this block (uniform)
         if (tid < 2) dsc[tid] = make_int4(0, 0, 0, 0);
         return;
     }
-    hi1 = block_reduce(hi1, red, false);
-    lo2 = block_reduce(lo2, red, true);
-    hi2 = block_reduce(hi2, red, false);
     const int e1 = hi1 - lo1 + W, e2 = hi2 - lo2 + W;   // box of cells touched
     float2 *grid = A.grid + (int64_t)c * A.n2 * A.n1;
 
@@ -267,10 +294,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
                         bhi = max(bhi, pm1[q]);
                     }
                 }
-                alo = block_reduce(alo, red, true);
-                ahi = block_reduce(ahi, red, false);
-                blo = block_reduce(blo, red, true);
-                bhi = block_reduce(bhi, red, false);
+                const int4 ab = block_min4(make_int4(alo, ~ahi, blo, ~bhi), red4);
+                alo = ab.x;
+                ahi = ~ab.y;
+                blo = ab.z;
+                bhi = ~ab.w;
                 const int e1a = ahi - alo + W, e1b = bhi - blo + W;
                 if (e1a * e2a + e1b * e2b <= kSlot && (ahi - alo + 1) + (bhi - blo + 1) <= kMaxCols &&
                     e1a + e1b <= kSpreadThreads && e1a <= A.n1 && e1b <= A.n1) {
