@@ -18,16 +18,16 @@
 //                   w x w kernel weights around (u' n1, v' n2); the points
 //                   are sorted by window column in LDS and every cell of the
 //                   block's bounding box gathers its sum in registers into
-//                   the block's tile slot (boxes of up to 1,024 cells; a
-//                   box taller than 16 rows whose points form two row groups
-//                   is split into two sub-boxes at the widest gap);
-//                   larger boxes add their sums, and boxes wider than the
-//                   grid (points over all beat frequencies, or across its
-//                   periodic edge) each weight, to the grid with atomics
-//   k_nufft_assemble  the tile slots added to the grid: four threads per cell
-//                   sum, in block order, a quarter each of the tiles whose box
-//                   covers it, and the quarters are added in a fixed order (no
-//                   atomics on the cells every block touches)
+//                   the block's tile slot (boxes of up to 1,024 cells and
+//                   512 columns; a box taller than 16 rows whose points form
+//                   two row groups is split into two sub-boxes at the widest
+//                   gap); larger boxes add their sums, and boxes wider than
+//                   the grid (points over all beat frequencies, or across
+//                   its periodic edge) each weight, to the grid with atomics
+//   k_nufft_assemble  the tile slots added to the grid: one or four threads
+//                   per cell sum, in block order, a share each of the tiles
+//                   whose box covers it, and the shares are added in a fixed
+//                   order (no atomics on the cells every block touches)
 //   k_nufft_rows    FFT (+ sign) of every grid row of length n1 in LDS that
 //                   some block wrote to; the Ns kept modes times the
 //                   deconvolution factor h / phi_hat go to a row buffer
@@ -57,7 +57,7 @@ constexpr int kSlot = 1024;                           // tile cells kept per (bl
 constexpr int kAccCells = 2048;                       // LDS accumulator cells of the column gather
 constexpr int kRowsReg = 16;                          // box rows held in registers by the column gather
 constexpr int kGapRows = 1024;                        // tallest box searched for a row gap to split at
-constexpr int kMaskBlocks = 1024;                     // blocks per coverage pass of a row
+constexpr int kMaskBlocks = 1024;                     // descriptor entries per coverage pass of a row
 constexpr int kAsmGroups = 8192;                      // assembly workgroups enough for 256 columns each
 constexpr int kAsmRows = 8;                           // grid rows per assembly workgroup
 constexpr int kFftThreads = 256;
