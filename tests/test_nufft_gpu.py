@@ -228,3 +228,28 @@ def test_largest_serving_request_sampled():
     rel, mx = errors(got[c, l, n], oracle.entries(big.radar, big.pixels, c, l, n))
     print(f"nufft largest request: relL2 {rel:.2e} maxabs {mx:.2e}", flush=True)
     assert rel <= 1e-6 + GATE_FP32
+    # every box fits a tile slot (after the splits): the sums have a fixed order
+    assert np.array_equal(got, _synth(big.radar, big.pixels, 1e-6))
+
+
+def test_boxes_wider_than_the_gathered_columns():
+    """A radar with N_s 512 (grid 1024 columns) and blocks whose points span
+    about 640 window columns: wider than the 512 columns a block gathers, not
+    wider than the grid; their weights go to the grid with atomics."""
+    rng = np.random.default_rng(480)
+    z = np.zeros((1, 3))
+    r = scenes.Radar(M=1, N=1, Ns=512, L=16, fc=77e9, mu=30e12, Fs=10e6, Tb=120e-6, tx=z, rx=z.copy())
+    P = 1024
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    Kb = 2 * r.mu / (r.c0 * r.Fs)
+    # beat frequencies 0.7 .. 1.3 cycles per sample (1.33 for odd pixels):
+    # reduced to -0.3 .. 0.33 around 0: 637-641 columns per block
+    span = np.where(np.arange(P) % 2 == 0, 0.6, 0.63)
+    rr = (0.7 + rng.uniform(0.0, 1.0, P) * span) / Kb
+    px = scenes.Pixels(f32(rr), f32(np.zeros(P)), f32(np.zeros(P)), f32(rng.lognormal(0, 0.5, P)),
+                       f32(rng.uniform(-0.02, 0.02, P)))
+    got = _synth(r, px, 1e-6)
+    rel_nu, _ = errors(got, onufft.nufft_cube(r, px, 1e-6))
+    rel, _ = errors(got, oracle.cube(r, px))
+    print(f"nufft wide boxes: vs NUFFT oracle {rel_nu:.2e}, vs exact {rel:.2e}", flush=True)
+    assert rel_nu <= GATE_FP32 and rel <= 1e-6 + GATE_FP32
