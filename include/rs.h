@@ -190,6 +190,21 @@ rs_status rs_plan_workspace_bytes(const rs_plan *plan, int64_t P, size_t *bytes)
 rs_status rs_plan_tune(rs_plan *plan, const rs_pixels *pixels, void *cube, int32_t reps,
                        void *hip_stream, char *chosen, size_t chosen_len);
 
+/* rs_plan_tune with a persistent cache of its choices: a text file at
+ * cache_path (host path), one entry per line "C Ns L Pb WNxTLxNW" keyed by
+ * the channel count, N_s, L and Pb, the pixel count rounded up to a power of
+ * two.  On a hit (the last well-formed line with the plan's key and a shape
+ * built into the library) the plan takes that shape and nothing is
+ * launched; on a miss the shape is tuned as rs_plan_tune does (the cube is
+ * synthesised) and the entry appended with one write.  A missing file is
+ * an empty cache; lines that do not parse are skipped.  Concurrent callers
+ * may both tune and both append; the later line wins.  Plans of the other
+ * forms are left unchanged (chosen: empty string, no file access).
+ * Errors: as rs_plan_tune, RS_E_INVALID for a NULL cache_path; a file that
+ * exists but cannot be read or appended to gives RS_E_INVALID. */
+rs_status rs_plan_tune_cached(rs_plan *plan, const rs_pixels *pixels, void *cube, int32_t reps,
+                              void *hip_stream, const char *cache_path, char *chosen, size_t chosen_len);
+
 /* Human-readable description of the plan (form, tile, chunking) into buf
  * (always NUL-terminated when len > 0).  Errors: RS_E_INVALID. */
 rs_status rs_plan_describe(const rs_plan *plan, int64_t P, char *buf, size_t len);

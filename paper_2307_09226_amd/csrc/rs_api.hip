@@ -2,6 +2,7 @@
 // synthesis.  All device work is enqueued on the caller's stream.
 #include "rs_api_internal.h"
 
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -522,6 +523,56 @@ extern "C" rs_status rs_plan_tune(rs_plan *pl, const rs_pixels *px, void *cube, 
         if (pl->form == RS_FORM_MFMA_SPLIT16) snprintf(chosen, chosen_len, "%dx%dx%d", pl->wn, pl->tl, pl->nw);
         else chosen[0] = '\0';
     }
+    return RS_OK;
+}
+
+extern "C" rs_status rs_plan_tune_cached(rs_plan *pl, const rs_pixels *px, void *cube, int32_t reps, void *stream,
+                                         const char *cache_path, char *chosen, size_t chosen_len)
+{
+    if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
+    if (!cache_path) return rs_fail(RS_E_INVALID, "cache_path is NULL");
+    if (reps < 1) return rs_fail(RS_E_INVALID, "reps < 1");
+    if (!cube) return rs_fail(RS_E_INVALID, "cube is NULL");
+    rs_status s = rs_check_pixels(pl, px);
+    if (s != RS_OK) return s;
+    if (pl->form != RS_FORM_MFMA_SPLIT16) {
+        if (chosen && chosen_len > 0) chosen[0] = '\0';
+        return RS_OK;
+    }
+    long long pb = 1;
+    while (pb < px->P) pb <<= 1;
+    // the last well-formed entry with this key and a built shape wins
+    int hit_wn = 0, hit_tl = 0, hit_nw = 0;
+    if (std::FILE *f = std::fopen(cache_path, "r")) {
+        char line[256];
+        while (std::fgets(line, sizeof line, f)) {
+            int c = 0, ns = 0, l = 0, wn = 0, tl = 0, nw = 0;
+            long long b = 0;
+            if (std::sscanf(line, "%d %d %d %lld %dx%dx%d", &c, &ns, &l, &b, &wn, &tl, &nw) == 7 && c == pl->C &&
+                ns == pl->Ns && l == pl->L && b == pb && rs_mfma_shape_supported(wn, tl, nw)) {
+                hit_wn = wn;
+                hit_tl = tl;
+                hit_nw = nw;
+            }
+        }
+        const bool bad = std::ferror(f) != 0;
+        std::fclose(f);
+        if (bad) return rs_fail(RS_E_INVALID, "cannot read the tile cache %s", cache_path);
+    } else if (errno != ENOENT) {
+        return rs_fail(RS_E_INVALID, "cannot open the tile cache %s", cache_path);
+    }
+    if (hit_wn) {
+        set_mfma_shape(pl, hit_wn, hit_tl, hit_nw);
+        if (chosen && chosen_len > 0) snprintf(chosen, chosen_len, "%dx%dx%d", pl->wn, pl->tl, pl->nw);
+        return RS_OK;
+    }
+    if ((s = rs_plan_tune(pl, px, cube, reps, stream, chosen, chosen_len)) != RS_OK) return s;
+    char entry[128];
+    snprintf(entry, sizeof entry, "%d %d %d %lld %dx%dx%d\n", pl->C, pl->Ns, pl->L, pb, pl->wn, pl->tl, pl->nw);
+    std::FILE *f = std::fopen(cache_path, "a");
+    const bool ok = f && std::fputs(entry, f) >= 0;
+    if (f && std::fclose(f) != 0) return rs_fail(RS_E_INVALID, "cannot append to the tile cache %s", cache_path);
+    if (!ok) return rs_fail(RS_E_INVALID, "cannot append to the tile cache %s", cache_path);
     return RS_OK;
 }
 

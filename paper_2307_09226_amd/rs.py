@@ -96,6 +96,8 @@ SIGNATURES = {
     "rs_plan_describe": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_char_p, ctypes.c_size_t]),
     "rs_plan_tune": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, ctypes.c_int32, _VP,
                                     ctypes.c_char_p, ctypes.c_size_t]),
+    "rs_plan_tune_cached": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, ctypes.c_int32, _VP,
+                                           ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]),
     "rs_beat_synthesize": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP]),
     "rs_beat_synthesize_ws": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP,
                                              ctypes.c_size_t, _VP]),
@@ -286,6 +288,17 @@ def rs_plan_tune(plan: Plan, pixels: DevicePixels, cube, reps: int = 3, stream=N
     buf = ctypes.create_string_buffer(32)
     _check(lib.rs_plan_tune(plan.handle, ctypes.byref(ps), _ptr(cube), int(reps), _stream_handle(stream),
                             buf, 32))
+    return buf.value.decode()
+
+
+def rs_plan_tune_cached(plan: Plan, pixels: DevicePixels, cube, cache_path: str, reps: int = 3,
+                        stream=None) -> str:
+    """rs_plan_tune with the persistent tile cache at cache_path (a hit sets
+    the stored shape and launches nothing); returns the shape."""
+    ps = pixels.struct(plan)
+    buf = ctypes.create_string_buffer(32)
+    _check(lib.rs_plan_tune_cached(plan.handle, ctypes.byref(ps), _ptr(cube), int(reps), _stream_handle(stream),
+                                   os.fsencode(cache_path), buf, 32))
     return buf.value.decode()
 
 

@@ -110,3 +110,4 @@ def test_nufft_plan_arguments_rejected_on_host():
 def test_tune_arguments_rejected_on_host():
     from paper_2307_09226_amd import rs
     assert rs.lib.rs_plan_tune(None, None, None, 3, None, None, 0) == rs.RS_E_INVALID
+    assert rs.lib.rs_plan_tune_cached(None, None, None, 3, None, b"/tmp/x", None, 0) == rs.RS_E_INVALID

@@ -49,3 +49,44 @@ def test_tune_leaves_other_forms_alone():
     before = plan.describe(px.P)
     rs.rs_plan_tune(plan, rs.DevicePixels.from_host(px), rs.new_cube(plan), reps=1)
     assert plan.describe(px.P) == before
+
+
+def test_tune_cache_miss_then_hit(tmp_path):
+    """rs_plan_tune_cached: a miss tunes and appends one entry; a later plan
+    with the same key takes the stored shape without launching anything and
+    then computes the same bits; lines that do not parse or name a shape the
+    library does not build are skipped; another pixel-count bucket misses."""
+    import torch
+    from paper_2307_09226_amd import rs
+    radar = scenes.radar_for(3, 4, 256, 64, Fs=10e6, Tb=120e-6)
+    px = scenes.tiny_scene(503, 9000, vmax=6.0)
+    d = rs.DevicePixels.from_host(px)
+    path = str(tmp_path / "tiles.txt")
+    plan1 = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
+    cube1 = rs.new_cube(plan1)
+    shape = rs.rs_plan_tune_cached(plan1, d, cube1, path, reps=2)
+    assert shape in SHAPES
+    lines = open(path).read().splitlines()
+    assert lines == [f"12 256 64 16384 {shape}"]
+    # noise after the entry: skipped
+    with open(path, "a") as f:
+        f.write("garbage line\n12 256 64 16384 48x128x8\n")
+    plan2 = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
+    cube2 = rs.new_cube(plan2)
+    cube2.fill_(complex(3.0, -1.0))
+    assert rs.rs_plan_tune_cached(plan2, d, cube2, path, reps=2) == shape
+    torch.cuda.synchronize()
+    assert torch.all(cube2 == complex(3.0, -1.0))          # a hit launches nothing
+    desc = json.loads(plan2.describe(px.P))
+    assert f"{desc['wave_rows']}x{desc['tile_l']}x{desc['waves']}" == shape
+    rs.rs_beat_synthesize(plan2, d, cube2)
+    torch.cuda.synchronize()
+    assert torch.equal(cube1, cube2)
+    assert len(open(path).read().splitlines()) == 3
+    # 20,000 pixels fall in the next bucket: a miss, one more entry
+    px3 = scenes.tiny_scene(504, 20000, vmax=6.0)
+    plan3 = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px3.P)
+    s3 = rs.rs_plan_tune_cached(plan3, rs.DevicePixels.from_host(px3), rs.new_cube(plan3), path, reps=1)
+    assert open(path).read().splitlines()[-1] == f"12 256 64 32768 {s3}"
+    for p in (plan1, plan2, plan3):
+        p.close()
