@@ -90,3 +90,37 @@ def test_tune_cache_miss_then_hit(tmp_path):
     assert open(path).read().splitlines()[-1] == f"12 256 64 32768 {s3}"
     for p in (plan1, plan2, plan3):
         p.close()
+
+
+@pytest.mark.parametrize("model", [0, 16])
+def test_every_tile_shape_full_cube(tmp_path, model):
+    """Each tile shape the library builds, forced through the tile cache, on
+    a radar whose n and l axes leave ragged tiles for every shape: the full
+    cube matches the oracle and a second run gives the same bits (a missing
+    barrier or a wrong tail guard in one shape shows up here)."""
+    import dataclasses
+    import torch
+    from paper_2307_09226_amd import rs
+    radar = dataclasses.replace(scenes.radar_for(2, 2, 130, 70, Fs=10e6, Tb=80e-6), model=model)
+    px = scenes.tiny_scene(505, 2333, vmax=6.0)
+    if model & 16:
+        px = scenes.block_strengths(px, radar.L, seed=6)
+    ref = oracle.cube(radar, px)
+    d = rs.DevicePixels.from_host(px)
+    for shape in sorted(SHAPES):
+        path = str(tmp_path / f"tiles_{shape}.txt")
+        with open(path, "w") as f:
+            f.write(f"4 130 70 4096 {shape}\n")
+        plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
+        cube = rs.new_cube(plan)
+        assert rs.rs_plan_tune_cached(plan, d, cube, path, reps=1) == shape
+        rs.rs_beat_synthesize(plan, d, cube)
+        again = rs.new_cube(plan)
+        rs.rs_beat_synthesize(plan, d, again)
+        torch.cuda.synchronize()
+        got = cube.cpu().numpy()
+        rel, mx = errors(got, ref)
+        print(f"tile {shape} model={model}: relL2 {rel:.2e} maxabs {mx:.2e}", flush=True)
+        assert rel <= GATE_MFMA and mx <= GATE_MFMA, shape
+        assert torch.equal(cube, again), shape
+        plan.close()
