@@ -363,19 +363,39 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     // reads the same keys at once, which the LDS broadcasts.  The records
     // (offsets from their sub-box's corner) are stored in sorted order so
     // that the gather reads them without an indirection.
+    // Each point also lays out its w2 at its row of the (sub-)box, 16 rows
+    // from its sorted position (what the register gather reads), into the
+    // space that held the keys and strengths: both are read first.
     static_assert(kSpreadThreads == kBlockPts, "one point per thread");
+    int rank = 0;
+    float2 cq = make_float2(0.f, 0.f);
     if (tid < npts) {
         const int k = key[tid];
         const int4 *k4 = reinterpret_cast<const int4 *>(key);
-        int rank = 0;
 #pragma unroll 4
         for (int i = 0; i < kBlockPts / 4; ++i) {
             const int4 v = k4[i];
             rank += (v.x < k) + (v.y < k) + (v.z < k) + (v.w < k);
         }
+        cq = pc[tid];
+    }
+    __syncthreads();   // every key and strength has been read
+    if (tid < npts) {
         const int g = group(tid);
-        srec[rank] = make_int2((pm1[tid] - blo1[g]) | ((pm2[tid] - blo2[g]) << 16), tid);
-        spc[rank] = pc[tid];
+        const int row = pm2[tid] - blo2[g];
+        srec[rank] = make_int2((pm1[tid] - blo1[g]) | (row << 16), tid);
+        spc[rank] = cq;
+        float4 *dst = reinterpret_cast<float4 *>(spw2r + rank * kRowsReg);
+#pragma unroll
+        for (int r4 = 0; r4 < kRowsReg / 4; ++r4) {
+            float w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int d = 4 * r4 + j - row;
+                w[j] = d >= 0 && d < W ? pw2[tid * W + d] : 0.f;
+            }
+            dst[r4] = make_float4(w[0], w[1], w[2], w[3]);
+        }
     }
     __syncthreads();
     // cs[k] = first sorted position whose column is >= k, k = 0 .. ncol
@@ -399,18 +419,12 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     const int E = e1 * e2;
     const int nparts = slot ? min(kSpreadThreads / e1, kAccCells / E) : 0;
     // (Sub-)boxes of at most 16 rows: the row sums of a column live in
-    // registers, and each point's w2 is laid out at its row offset once per
-    // block so that a candidate costs four LDS vector reads and 32 FMAs.  TWO
+    // registers, and each point's w2 is laid out at its row offset (by the
+    // sort) so that a candidate costs four LDS vector reads and 32 FMAs.  TWO
     // (two sub-boxes) is a compile-time flag, so that the one-box case keeps
     // its simple indexing.
     auto register_gather = [&](auto two_t) {
         constexpr bool TWO = decltype(two_t)::value;
-        for (int k = tid; k < npts * kRowsReg; k += kSpreadThreads) {
-            const int s = k / kRowsReg, rr = k % kRowsReg;
-            const int2 rec = srec[s];
-            const int d = rr - (rec.x >> 16);
-            spw2r[k] = d >= 0 && d < W ? pw2[rec.y * W + d] : 0.f;
-        }
         // threads, shares and accumulator cells of the sub-boxes: the first
         // takes threads in proportion to its points (at least a column's
         // worth each), its shares leave room for one of the second
@@ -419,7 +433,6 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
         const int tA = TWO ? min(max(kSpreadThreads * nA / npts, be1[0]), kSpreadThreads - be1[1]) : kSpreadThreads;
         const int pA = min(tA / be1[0], (kAccCells - EB) / EA);
         const int pB = TWO ? min((kSpreadThreads - tA) / be1[1], (kAccCells - pA * EA) / EB) : 0;
-        __syncthreads();
         const int g = TWO && tid >= tA ? 1 : 0;
         const int tl = g ? tid - tA : tid;
         const int ex = g ? be1[1] : be1[0], ey = g ? be2[1] : be2[0];
