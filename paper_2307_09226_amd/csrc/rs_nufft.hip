@@ -323,9 +323,10 @@ __global__ __launch_bounds__(kSpreadThreads) void k_nufft_spread(nu_args A)
     }
     // flag the grid rows this block writes to (every row when the box is
     // taller than the grid): the FFT passes skip the rows no block touches
+    // (every writer stores the same 1 into a cleared flag: plain stores)
     for (int sb = 0; sb < nsb; ++sb)
         for (int t = tid; t < min(be2[sb], A.n2); t += kSpreadThreads)
-            atomicOr(A.rowcov + (int64_t)c * A.n2 + pmod(blo2[sb] + t, A.n2), 1);
+            A.rowcov[(int64_t)c * A.n2 + pmod(blo2[sb] + t, A.n2)] = 1;
     if (nsb == 1 && (hi1 - lo1 >= kMaxCols || e1 > A.n1 || e2 > A.n2)) {
         // box wider than the grid or the column table: scatter each weight
         // to the grid (a lane per window cell, a wave per point)
