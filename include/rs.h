@@ -47,9 +47,11 @@
  *                         C Ns L log, not P C Ns L.  The grid sums are
  *                         formed in a fixed order (bitwise reproducible)
  *                         while each 256-pixel block's box of grid cells
- *                         fits 1,024 cells; larger boxes are added with
- *                         atomics and then the last bits vary from run to
- *                         run.  Workspace grows with P (8 KiB per block and
+ *                         (or its two sub-boxes, for a block whose points
+ *                         fall into two row groups) fits 1,024 cells and
+ *                         512 columns; larger boxes are added with atomics
+ *                         and then the last bits vary from run to run.
+ *                         Workspace grows with P (8 KiB per block and
  *                         channel).  Limits: Ns, L <= 2048, strengths
  *                         constant over the blocks, single-frame calls
  *                         only (batch and sessions: RS_E_UNSUPPORTED).
@@ -167,7 +169,8 @@ rs_status rs_cube_plan(const rs_radar *radar, rs_form form, rs_dtype dtype,
  * grid the smallest power of two >= max(2 Ns, 2 w) by >= max(2 L, 2 w).
  * Errors: as rs_cube_plan, RS_E_INVALID for a tolerance outside the range,
  * RS_E_UNSUPPORTED for RS_MODEL_BLOCK_STRENGTH, Ns or L > 2048, more than
- * 65,535 channels or max_pixels >= 2^31. */
+ * 65,535 channels, max_pixels >= 2^31, or channels x grid rows (in l) or
+ * channels x Ns reaching 2^24. */
 rs_status rs_cube_plan_nufft(const rs_radar *radar, rs_dtype dtype, int64_t max_pixels,
                              double tolerance, rs_plan **out);
 
