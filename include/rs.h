@@ -53,8 +53,8 @@
  *                         and then the last bits vary from run to run.
  *                         Workspace grows with P (8 KiB per block and
  *                         channel).  Limits: Ns, L <= 2048, strengths
- *                         constant over the blocks, single-frame calls
- *                         only (batch and sessions: RS_E_UNSUPPORTED).
+ *                         constant over the blocks; batches run frame by
+ *                         frame, sessions are refused (RS_E_UNSUPPORTED).
  *
  * Conventions
  *   - Every call returns rs_status; nothing throws or aborts across the ABI.
@@ -227,10 +227,12 @@ rs_status rs_beat_synthesize_ws(rs_plan *plan, const rs_pixels *pixels, void *cu
 
 /* Enqueue `nframes` cubes that share one plan (e.g. consecutive animation
  * frames with different pixel counts) as ONE persistent launch over all
- * frames' work items plus one reduction launch.  frames: HOST array of
+ * frames' work items plus one reduction launch (NUFFT plans: the frames'
+ * launches one after another on one workspace).  frames: HOST array of
  * nframes rs_pixels (device pointers inside); cubes: device buffer of
  * nframes consecutive cubes.  Each frame's cube is bitwise identical to
- * rs_beat_synthesize on that frame alone.
+ * rs_beat_synthesize on that frame alone (for the NUFFT form where every
+ * box fits its tile slot, as there).
  * Errors: as rs_beat_synthesize, plus nframes < 0. */
 rs_status rs_beat_synthesize_batch(rs_plan *plan, const rs_pixels *frames, int32_t nframes,
                                    void *cubes, void *hip_stream);

@@ -644,14 +644,30 @@ extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *fram
     if (nframes < 0) return rs_fail(RS_E_INVALID, "nframes < 0");
     if (nframes == 0) return RS_OK;
     if (!frames || !cubes) return rs_fail(RS_E_INVALID, "NULL frames or cubes");
-    if (pl->form == RS_FORM_NUFFT)
-        return rs_fail(RS_E_UNSUPPORTED, "batched frames serve the direct forms; call rs_beat_synthesize per frame");
     rs_status s;
     for (int f = 0; f < nframes; ++f)
         if ((s = rs_check_pixels(pl, &frames[f])) != RS_OK) return s;
     device_guard g(pl->device);
     if (g.st != RS_OK) return g.st;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const size_t cube_bytes_f = (size_t)pl->C * pl->L * pl->Ns * (pl->dtype == RS_C128 ? 16 : 8);
+    if (pl->form == RS_FORM_NUFFT) {
+        // the frames one after another on one workspace sized for the largest
+        int64_t pmax = 0;
+        for (int f = 0; f < nframes; ++f) pmax = frames[f].P > pmax ? frames[f].P : pmax;
+        const size_t need = rs_nufft_workspace(pl, pmax);
+        void *ws = nullptr;
+        if (need > 0 && hipMallocAsync(&ws, need, st) != hipSuccess)
+            return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", need);
+        s = RS_OK;
+        for (int f = 0; f < nframes && s == RS_OK; ++f)
+            s = rs_nufft_enqueue(pl, &frames[f], static_cast<char *>(cubes) + f * cube_bytes_f, ws, st);
+        if (ws) {
+            const hipError_t e = hipFreeAsync(ws, st);
+            if (e != hipSuccess && s == RS_OK) s = rs_fail(RS_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
+        }
+        return s;
+    }
 
     const size_t cube_bytes = (size_t)pl->C * pl->L * pl->Ns * (pl->dtype == RS_C128 ? 16 : 8);
     std::vector<rs_job> jobs(nframes);

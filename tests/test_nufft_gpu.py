@@ -114,8 +114,8 @@ def test_frame_sampled():
 
 def test_edge_sizes_and_refusals():
     """P = 0 gives an exact zero cube; one pixel and a pixel count that
-    leaves a partial block match the oracle; batches, sessions and
-    strengths per block are refused."""
+    leaves a partial block match the oracle; sessions and strengths per
+    block are refused."""
     import ctypes
     import torch
     rs = _rs()
@@ -129,9 +129,6 @@ def test_edge_sizes_and_refusals():
     plan = rs.rs_cube_plan_nufft(r, 0, max_pixels=10, tolerance=1e-4)
     d = rs.DevicePixels.from_host(scenes.tiny_scene(450, 10))
     cubes = rs.new_cube(plan, count=2)
-    with pytest.raises(rs.RSError) as e:
-        rs.rs_beat_synthesize_batch(plan, [d, d], cubes)
-    assert e.value.status == rs.RS_E_UNSUPPORTED
     sess = rs.Session(hbm_budget=1 << 28, max_slots=1)
     with pytest.raises(rs.RSError) as e:
         sess.submit(plan, d, cubes[0])
@@ -253,3 +250,30 @@ def test_boxes_wider_than_the_gathered_columns():
     rel, _ = errors(got, oracle.cube(r, px))
     print(f"nufft wide boxes: vs NUFFT oracle {rel_nu:.2e}, vs exact {rel:.2e}", flush=True)
     assert rel_nu <= GATE_FP32 and rel <= 1e-6 + GATE_FP32
+
+
+def test_batch_equals_single_frames_bitwise():
+    """Frames of different pixel counts (room+pedestrian renders: every box
+    fits its tile slot, so the sums have a fixed order; one frame empty, one
+    a partial block) through one batched call give each frame's single-call
+    cube bit for bit, in complex64 and complex128."""
+    import torch
+    rs = _rs()
+    r, full = scenes.workload_frame()
+    frames = [full.take(np.arange(9000)), scenes.Pixels(*(np.zeros(0, np.float32) for _ in range(5))),
+              full.take(np.arange(30000, 30077)), full]
+    for dtype in (0, 1):
+        plan = rs.rs_cube_plan_nufft(r, dtype, max_pixels=max(f.P for f in frames), tolerance=1e-5)
+        dev = [rs.DevicePixels.from_host(f) for f in frames]
+        cubes = rs.new_cube(plan, count=len(frames))
+        cubes.fill_(complex(5.0, 5.0))
+        rs.rs_beat_synthesize_batch(plan, dev, cubes)
+        for i, d in enumerate(dev):
+            one = rs.new_cube(plan)
+            rs.rs_beat_synthesize(plan, d, one)
+            torch.cuda.synchronize()
+            assert torch.equal(cubes[i], one), (dtype, i)
+        assert torch.all(cubes[1] == 0)
+        rel, _ = errors(cubes[2].cpu().numpy(), oracle.cube(r, frames[2]))
+        assert rel <= 1e-5 + GATE_FP32
+        plan.close()
