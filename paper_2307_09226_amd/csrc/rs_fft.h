@@ -20,10 +20,12 @@ static __device__ void twiddles(float2 *tw, int n, double sign)
 }
 
 // In-place radix-2 DIT over `rows` rows of length n = 2^logn, stored with
-// row stride n in LDS, input in bit-reversed order.  tw = twiddles of n.
-static __device__ void fft_rows(float2 *x, int rows, int logn, const float2 *tw)
+// row stride `stride` (n when 0) in LDS, input in bit-reversed order.
+// tw = twiddles of n.
+static __device__ void fft_rows(float2 *x, int rows, int logn, const float2 *tw, int stride = 0)
 {
     const int n = 1 << logn;
+    const int rs = stride ? stride : n;
     const int nb = rows * (n >> 1);  // butterflies per stage
     for (int s = 0; s < logn; ++s) {
         const int half = 1 << s;
@@ -33,7 +35,7 @@ static __device__ void fft_rows(float2 *x, int rows, int logn, const float2 *tw)
             const int bb = b & ((n >> 1) - 1);
             const int pos = bb & (half - 1);
             const int i = ((bb >> s) << (s + 1)) + pos;
-            float2 *r = x + row * n;
+            float2 *r = x + row * rs;
             const float2 t = cmul(tw[pos * tstride], r[i + half]);
             const float2 u = r[i];
             r[i] = make_float2(u.x + t.x, u.y + t.y);

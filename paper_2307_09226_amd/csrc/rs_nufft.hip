@@ -778,7 +778,9 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_cols(nu_args A, int logn2
     extern __shared__ float2 smem[];
     const int n2 = 1 << logn2;
     float2 *tw = smem;
-    float2 *x = smem + n2 / 2;  // [kb][n2]
+    // [kb][n2 + 1]: the padding puts the columns' equal offsets in different banks
+    const int xs = n2 + 1;
+    float2 *x = smem + n2 / 2;
     const int c = blockIdx.x / groups;
     const int n0 = (blockIdx.x % groups) * kb;
     const int kn = min(kb, A.Ns - n0);
@@ -791,18 +793,18 @@ __global__ __launch_bounds__(kFftThreads) void k_nufft_cols(nu_args A, int logn2
     for (int e = threadIdx.x; e < n2 * kb; e += blockDim.x) {
         const int m2 = e >> logkb, kk = e & (kb - 1);
         // untouched rows are zero (their row-buffer entries were never written)
-        x[kk * n2 + bitrev(m2, logn2)] =
+        x[kk * xs + bitrev(m2, logn2)] =
             kk < kn && live[m2] ? rs_gload2(src, (int64_t)m2 * A.Ns + kk) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    fft_rows(x, kb, logn2, tw);
+    fft_rows(x, kb, logn2, tw, xs);
     const int h = A.L / 2;
     OT *out = reinterpret_cast<OT *>(A.cube) + (int64_t)c * A.L * A.Ns + n0;
     for (int e = threadIdx.x; e < A.L * kb; e += blockDim.x) {
         const int l = e >> logkb, kk = e & (kb - 1);
         if (kk >= kn) continue;
         const int k = l - h;
-        const float2 v = x[kk * n2 + (k < 0 ? k + n2 : k)];
+        const float2 v = x[kk * xs + (k < 0 ? k + n2 : k)];
         const float d = rs_gload(A.d2, l);
         OT o;
         o.x = v.x * d;
@@ -979,7 +981,7 @@ rs_status rs_nufft_enqueue(const rs_plan *pl, const rs_pixels *px, void *cube, v
                        logn1, rpw, rows_total);
     const int kb = std::max(1, std::min(4, 1024 / pl->nu_n2));
     const int groups = (pl->Ns + kb - 1) / kb;
-    const size_t lds2 = (size_t)(pl->nu_n2 / 2 + kb * pl->nu_n2) * sizeof(float2);
+    const size_t lds2 = (size_t)(pl->nu_n2 / 2 + kb * (pl->nu_n2 + 1)) * sizeof(float2);
     if (pl->dtype == RS_C128)
         hipLaunchKernelGGL(k_nufft_cols<double2>, dim3((unsigned)(pl->C * groups)), dim3(kFftThreads), lds2, st, A,
                            logn2, kb, groups);
