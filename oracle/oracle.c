@@ -33,11 +33,17 @@
  * Signal-model variants (bit flags in orc_radar.model; 0 = the model above).
  * Each changes only the per-(pixel, channel) arguments psi and b, evaluated
  * in binary64 in this order:
- *   FAR_FIELD (1)   eq. (2) read literally: the beat frequency uses the
- *                   range from the array origin Rp = |x| and the carrier
- *                   phase its first-order expansion over the array,
- *                   Rc = Rp - u.(tx_m + rx_r)/2 with u = x/Rp (eq. (2)'s
- *                   angle-of-arrival term); psi = Rc Kc, b = Rp Kb
+ *   FAR_FIELD (1)   eq. (2): the range is the one from the array origin,
+ *                   Rp = |x|, for the beat frequency (b = Rp Kb) and the
+ *                   carrier phase, and the channels differ by eq. (2)'s
+ *                   angle-of-arrival term, the first-order path change
+ *                   across the array -u.(tx_m + rx_r)/2 (u = x/Rp) in
+ *                   wavelengths:  psi = Rp Kc - s Ka,
+ *                   s = u.(tx_m + rx_r)/2, Ka = (2 fc)/c0 whatever
+ *                   carrier_phase says.  With carrier_phase == 0 this is
+ *                   eq. (2) as printed (sigma = a, no common phase
+ *                   2 Rp / lambda); with carrier_phase == 1 it is the
+ *                   far-field limit of the exact model above
  *   RVP (8)         residual video phase of the dechirped signal,
  *                   -mu tau^2 / 2 with tau = 2 R / c0:  psi -= (R R) Krvp,
  *                   Krvp = (2 mu)/(c0 c0), R the beat range
@@ -92,7 +98,7 @@ static void orc_set_threads(int nthreads)
 
 /* Plan constants of the recipe. */
 typedef struct {
-    double Kc, Kb, Kd, Kf, Krvp;
+    double Kc, Kb, Kd, Kf, Krvp, Ka;
 } orc_consts;
 
 static void constants(const orc_radar *r, orc_consts *k)
@@ -102,6 +108,7 @@ static void constants(const orc_radar *r, orc_consts *k)
     k->Kd = ((2.0 * r->fc) * r->Tb) / r->c0;
     k->Kf = (2.0 * r->fc) / (r->c0 * r->Fs);
     k->Krvp = (2.0 * r->mu) / (r->c0 * r->c0);
+    k->Ka = (2.0 * r->fc) / r->c0;
 }
 
 /* Euclidean distance from a float32 pixel position to an antenna. */
@@ -124,22 +131,22 @@ static void chan_args(const orc_radar *r, const orc_consts *k, const orc_pixels 
     int m = c / r->N, rr = c % r->N;
     const double *tx = r->tx + 3 * m, *rx = r->rx + 3 * rr;
     double v = (double)px->vr[p];
-    double Rc, Rb;
+    double Rb, ps;
     if (r->model & ORC_FAR_FIELD) {
         double x = (double)px->x[p], y = (double)px->y[p], z = (double)px->z[p];
         double Rp = sqrt((x * x + y * y) + z * z);
         double ux = x / Rp, uy = y / Rp, uz = z / Rp;
         double s = 0.5 * ((ux * (tx[0] + rx[0]) + uy * (tx[1] + rx[1])) + uz * (tx[2] + rx[2]));
-        Rc = Rp - s;
+        ps = Rp * k->Kc - s * k->Ka;
         Rb = Rp;
     } else {
         double rt = distance(px->x[p], px->y[p], px->z[p], tx);
         double rv = distance(px->x[p], px->y[p], px->z[p], rx);
-        Rc = 0.5 * (rt + rv);
-        Rb = Rc;
+        Rb = 0.5 * (rt + rv);
+        ps = Rb * k->Kc;
     }
     *beta = v * k->Kd;
-    *psi = Rc * k->Kc;
+    *psi = ps;
     *b = Rb * k->Kb;
     if (r->model & ORC_RVP) *psi = *psi - (Rb * Rb) * k->Krvp;
     if (r->model & ORC_TDM_SLOT) *psi = *psi - *beta * ((double)m / (double)r->M);

@@ -166,29 +166,112 @@ def pin_doppler_alias(o):
     assert relerr(o.cube(r, p3), o.cube(r, p1)) > 0.1
 
 
-def pin_eq1_per_rx(o):
-    """Summing the virtual channels of one Rx over the Tx reproduces eq. (1)
-    for that Rx: h_r(n; l) = sum_m sigma_{m,r} exp(j2pi(2 mu R_{m,r} n /(c Fs)
-    - f_D l Tb)), with sigma carrying the carrier phase 2 fc R / c."""
-    rng = np.random.default_rng(8)
-    r = scenes.radar_for(3, 4, 8, 4, Fs=10e6, Tb=120e-6)
-    r.tx, r.rx = _random_antennas(rng, 3, 4, r.wavelength)
-    px = scenes.tiny_scene(9, 6)
+def _eq2_as_printed(r, px, q):
+    """Eq. (2) for Rx n = q + 1 written out with its own 1-based indices and
+    evaluated in 40-digit arithmetic from the float32 pixels:
+      H[l][n_s] = sum_p sum_{m=1..M} P_r exp(j2pi(2 mu R/c (n_s-1)/F_s
+                  - 2 f V/c (l-1) T_b + ((m-1)N + n - 1) dd sin(theta)/lambda))
+    with R = |x| the pixel's range, dd = lambda/2, the Doppler of eq. (1)
+    (f = f_c, no 1/L: the garbles read as such) and sin(theta) = -x/R, the
+    direction cosine along the array axis with theta measured toward -x
+    (the sign that makes eq. (2)'s '+' agree with a phase that grows with
+    the path length)."""
+    out = np.zeros((r.L, r.Ns), dtype=np.complex128)
+    with mp.workdps(40):
+        c0, fc, mu, Fs, Tb = (mp.mpf(float(v)) for v in (r.c0, r.fc, r.mu, r.Fs, r.Tb))
+        lam = c0 / fc
+        dd = lam / 2
+        n = q + 1
+        for p in range(px.P):
+            pos = [mp.mpf(float(v)) for v in (px.x[p], px.y[p], px.z[p])]
+            R = mp.sqrt(sum(t * t for t in pos))
+            sin_t = -pos[0] / R
+            V = mp.mpf(float(px.vr[p]))
+            Pr = mp.mpf(float(px.amp[p]))
+            for l in range(1, r.L + 1):
+                for ns in range(1, r.Ns + 1):
+                    acc = mp.mpc(0)
+                    for m in range(1, r.M + 1):
+                        ph = (2 * mu * R / c0 * (ns - 1) / Fs - 2 * fc * V / c0 * (l - 1) * Tb
+                              + ((m - 1) * r.N + n - 1) * dd / lam * sin_t)
+                        acc += Pr * mp.expj(2 * mp.pi * ph)
+                    out[l - 1, ns - 1] += complex(acc)
+    return out
+
+
+def pin_eq2_literal(o):
+    """The far-field variant without the carrier phase is eq. (2) as printed:
+    for each Rx, the sum of its virtual channels over the Tx equals eq. (2)'s
+    H_{T_n} (written out above, independently of the oracle) within the
+    binary64 rounding of the phase arguments, on a small moving scene and
+    the A11 virtual ULA."""
+    r = _with_model(scenes.radar_for(2, 3, 6, 4, Fs=10e6, Tb=120e-6, carrier_phase=0), 1)
+    px = scenes.tiny_scene(91, 4, vmax=4.0)
     Y = o.cube(r, px)
-    pos = np.stack([px.x, px.y, px.z], axis=1).astype(np.float64)
-    n = np.arange(r.Ns)
-    l = np.arange(r.L)
+    scale = r.M * float(np.sum(px.amp))
     for q in range(r.N):
-        h = np.zeros((r.L, r.Ns), dtype=np.complex128)
-        for m in range(r.M):
-            R = 0.5 * (np.linalg.norm(pos - r.tx[m], axis=1) + np.linalg.norm(pos - r.rx[q], axis=1))
-            fD = 2 * px.vr.astype(np.float64) * r.fc / r.c0
-            for p in range(px.P):
-                sigma = px.amp[p] * np.exp(2j * np.pi * 2 * r.fc * R[p] / r.c0)
-                h += sigma * np.exp(2j * np.pi * (2 * r.mu * R[p] / r.c0 * n[None, :] / r.Fs
-                                                  - fD[p] * l[:, None] * r.Tb))
         got = sum(Y[m * r.N + q] for m in range(r.M))
-        assert relerr(got, h) < 1e-8, (q, relerr(got, h))
+        want = _eq2_as_printed(r, px, q)
+        assert np.max(np.abs(got - want)) < 1e-12 * scale, (q, float(np.max(np.abs(got - want))))
+
+
+def pin_eq1_per_rx(o):
+    """Summing the virtual channels of one Rx over the Tx gives eq. (1) for
+    that Rx, written out with its own 1-based indices and evaluated in
+    40-digit arithmetic: h_{T,n}(n_s; l) = sum_m sigma_{m,n}
+    exp(j2pi(2 mu R_{m,n}/c (n_s-1)/F_s - f_D (l-1) T_b)), summed over the
+    pixels, with sigma = a exp(j2pi 2 f_c R_{m,n}/c) (the carrier phase) and
+    f_D = 2 v f_c / c.  Random non-collinear antennas, so a transposed
+    channel index or a Tx/Rx mix-up shows."""
+    rng = np.random.default_rng(8)
+    r = scenes.radar_for(2, 3, 4, 3, Fs=10e6, Tb=120e-6)
+    r.tx, r.rx = _random_antennas(rng, 2, 3, r.wavelength)
+    px = scenes.tiny_scene(9, 3)
+    Y = o.cube(r, px)
+    with mp.workdps(40):
+        c0, fc, mu, Fs, Tb = (mp.mpf(float(v)) for v in (r.c0, r.fc, r.mu, r.Fs, r.Tb))
+        for n in range(1, r.N + 1):
+            want = np.zeros((r.L, r.Ns), dtype=np.complex128)
+            for p in range(px.P):
+                pos = [mp.mpf(float(v)) for v in (px.x[p], px.y[p], px.z[p])]
+                fD = 2 * mp.mpf(float(px.vr[p])) * fc / c0
+                for m in range(1, r.M + 1):
+                    tx = [mp.mpf(float(v)) for v in r.tx[m - 1]]
+                    rx = [mp.mpf(float(v)) for v in r.rx[n - 1]]
+                    R = (mp.sqrt(sum((pos[k] - tx[k]) ** 2 for k in range(3)))
+                         + mp.sqrt(sum((pos[k] - rx[k]) ** 2 for k in range(3)))) / 2
+                    sigma = mp.mpf(float(px.amp[p])) * mp.expj(2 * mp.pi * 2 * fc * R / c0)
+                    for l in range(1, r.L + 1):
+                        for ns in range(1, r.Ns + 1):
+                            want[l - 1, ns - 1] += complex(sigma * mp.expj(
+                                2 * mp.pi * (2 * mu * R / c0 * (ns - 1) / Fs - fD * (l - 1) * Tb)))
+            got = sum(Y[(m - 1) * r.N + (n - 1)] for m in range(1, r.M + 1))
+            scale = r.M * float(np.sum(px.amp))
+            assert np.max(np.abs(got - want)) < 1e-10 * scale, (n, float(np.max(np.abs(got - want))))
+
+
+def pin_far_field_literal_one_pixel(o):
+    """One pixel, far-field variant, no carrier phase: channel 0 (Tx 0 and
+    Rx 0 at the origin) at n = l = 0 is exactly the real strength (eq. (2)
+    has no common phase), and channel c is a exp(j2pi c sin(theta) / 2)
+    (eq. (2)'s angle term with dd = lambda/2) at any distance, near or far;
+    along fast time the phase advances by 2 mu R / (c0 Fs) per sample."""
+    r = _with_model(scenes.radar_for(3, 4, 8, 4, Fs=10e6, Tb=120e-6, carrier_phase=0), 1)
+    for dist in (1.5, 300.0):
+        az, el = math.radians(-25.0), math.radians(8.0)
+        u = np.array([math.cos(el) * math.sin(az), math.cos(el) * math.cos(az), math.sin(el)])
+        px = _one_pixel(*(dist * u), 0.75, 0.0)
+        Y = o.cube(r, px)
+        assert Y[0, 0, 0] == complex(0.75, 0.0), Y[0, 0, 0]
+        x = np.array([float(px.x[0]), float(px.y[0]), float(px.z[0])])
+        R = np.linalg.norm(x)
+        sin_t = -x[0] / R
+        for c in range(r.C):
+            want = 0.75 * np.exp(2j * np.pi * c * sin_t / 2)
+            assert abs(Y[c, 0, 0] - want) < 1e-13, (dist, c, Y[c, 0, 0], want)
+        b = 2 * r.mu * R / (r.c0 * r.Fs)
+        step = Y[7, 0, 1:] / Y[7, 0, :-1]
+        assert np.max(np.abs(np.angle(step / np.exp(2j * np.pi * b)))) < 1e-12
 
 
 def pin_far_field(o):
@@ -334,11 +417,13 @@ def pin_dechirp_physics(o):
 
 
 def pin_far_field_model(o):
-    """Far-field variant (eq. (2) read literally): across the virtual ULA the
-    channels differ at n = l = 0 by exactly eq. (2)'s angle term
-    exp(-j2pi c (lambda/2) u_x / lambda) at any distance; along fast time the
-    phase advances by 2 mu |x| / (c0 Fs) per sample, the range from the array
-    origin; and the variant approaches the exact model as 1/distance."""
+    """Far-field variant with the carrier phase (the far-field limit of the
+    exact model): across the virtual ULA the channels differ at n = l = 0 by
+    exactly eq. (2)'s angle term exp(-j2pi c (lambda/2) u_x / lambda) at any
+    distance (the common phase 2 |x| / lambda cancels in the ratio); along
+    fast time the phase advances by 2 mu |x| / (c0 Fs) per sample, the range
+    from the array origin; and the variant approaches the exact model as
+    1/distance."""
     r = _with_model(scenes.radar_for(3, 4, 16, 2, Fs=10e6, Tb=120e-6), 1)
     lam = r.wavelength
     for dist in (2.0, 40.0):
@@ -446,5 +531,5 @@ ALL_PINS = [pin_block_strength_reductions, pin_block_strength_sidebands, pin_blo
             pin_model_zero_is_default, pin_slot_timing_alias, pin_dechirp_physics,
             pin_far_field_model, pin_empty_scene, pin_single_scatterer_closed_form, pin_range_and_doppler_peaks,
             pin_marginals, pin_linearity, pin_static_scene_slices, pin_doppler_alias,
-            pin_eq1_per_rx, pin_far_field, pin_entries_match_cube, pin_brute_recipe,
+            pin_eq1_per_rx, pin_eq2_literal, pin_far_field_literal_one_pixel, pin_far_field, pin_entries_match_cube, pin_brute_recipe,
             pin_brute_exact, pin_brute_exact_no_carrier]

@@ -11,8 +11,8 @@ import pins
 # (name, original text, replacement): a dropped term, a wrong sign, a wrong
 # or transposed index, a wrong scale, a mistake in a closed form.
 MUTANTS = [
-    ("rx_ignored", "Rc = 0.5 * (rt + rv);", "Rc = 0.5 * (rt + rt);"),
-    ("full_path_not_half", "Rc = 0.5 * (rt + rv);", "Rc = (rt + rv);"),
+    ("rx_ignored", "Rb = 0.5 * (rt + rv);", "Rb = 0.5 * (rt + rt);"),
+    ("full_path_not_half", "Rb = 0.5 * (rt + rv);", "Rb = (rt + rv);"),
     ("doppler_sign", "double phi = (psi_f + th_f) - ph_f;", "double phi = (psi_f + th_f) + ph_f;"),
     ("beat_sign", "double phi = (psi_f + th_f) - ph_f;", "double phi = (psi_f - th_f) - ph_f;"),
     ("channel_transposed", "int m = c / r->N, rr = c % r->N;", "int m = c % r->M, rr = c / r->M;"),
@@ -46,9 +46,12 @@ MUTANTS = [
     ("intra_uses_beat_constant", "*b = *b - v * k->Kf;", "*b = *b - v * k->Kb;"),
     ("rvp_sign", "*psi = *psi - (Rb * Rb) * k->Krvp;", "*psi = *psi + (Rb * Rb) * k->Krvp;"),
     ("rvp_factor", "k->Krvp = (2.0 * r->mu) / (r->c0 * r->c0);", "k->Krvp = (r->mu) / (r->c0 * r->c0);"),
-    ("ff_beat_uses_carrier_range", "Rb = Rp;", "Rb = Rc;"),
+    ("ff_beat_uses_expanded_range", "Rb = Rp;", "Rb = Rp - s;"),
     ("ff_no_half", "double s = 0.5 * ((ux", "double s = ((ux"),
-    ("ff_sign", "Rc = Rp - s;", "Rc = Rp + s;"),
+    ("ff_sign", "ps = Rp * k->Kc - s * k->Ka;", "ps = Rp * k->Kc + s * k->Ka;"),
+    ("ff_angle_scaled_by_carrier_switch", "ps = Rp * k->Kc - s * k->Ka;", "ps = (Rp - s) * k->Kc;"),
+    ("ff_common_phase_always", "ps = Rp * k->Kc - s * k->Ka;", "ps = (Rp - s) * k->Ka;"),
+    ("ff_angle_half_wavelength", "k->Ka = (2.0 * r->fc) / r->c0;", "k->Ka = r->fc / r->c0;"),
     ("block_strength_ignored", "if (r->model & ORC_BLOCK_STRENGTH) return", "if (0) return"),
     ("block_strength_transposed", "px->amp[(int64_t)l * px->P + p]", "px->amp[(int64_t)p * r->L + l]"),
     ("block_strength_next_block", "px->amp[(int64_t)l * px->P + p]",
