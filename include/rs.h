@@ -97,13 +97,20 @@ typedef enum { RS_C64 = 0, RS_C128 = 1 } rs_dtype; /* interleaved (re, im) */
 /* Signal-model variants (bit flags, rs_radar.model; 0 = the model above).
  * Each changes only the per-(pixel, channel) phase arguments psi and b, in
  * binary64, in this order:
- *   RS_MODEL_FAR_FIELD    eq. (2) read literally: the beat frequency uses
- *                         the range from the array origin Rp = |x| and the
- *                         carrier phase its first-order expansion over the
- *                         array, Rc = Rp - u.(tx_m + rx_r)/2 with u = x/Rp
- *                         (eq. (2)'s angle-of-arrival term):
- *                         psi = Rc Kc, b = Rp Kb.  Pixels must not sit at
- *                         the origin.
+ *   RS_MODEL_FAR_FIELD    eq. (2): the beat frequency and the carrier
+ *                         phase use the range from the array origin
+ *                         Rp = |x|, and the channels differ by eq. (2)'s
+ *                         angle-of-arrival term, the first-order path
+ *                         change across the array:
+ *                         psi = Rp Kc - s (2 fc / c0), b = Rp Kb, with
+ *                         s = u.(tx_m + rx_r)/2 and u = x / Rp.  With
+ *                         carrier_phase = 0 (Kc = 0) this is eq. (2) as
+ *                         printed: sigma = a, and channel c = m N + r of a
+ *                         lambda/2 ULA on +x gets the phase c sin(theta)/2
+ *                         with sin(theta) = -u_x (theta measured toward -x).
+ *                         With carrier_phase = 1 it is the far-field limit
+ *                         of the exact model.  Pixels must not sit at the
+ *                         origin.
  *   RS_MODEL_RVP          residual video phase of the dechirped echo,
  *                         -mu tau^2 / 2 with tau = 2 R / c0:
  *                         psi -= R^2 (2 mu / c0^2), R the beat range

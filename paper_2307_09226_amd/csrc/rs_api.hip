@@ -95,6 +95,7 @@ rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *par
     j.Kd = pl->Kd;
     j.Kf = pl->Kf;
     j.Krvp = pl->Krvp;
+    j.Ka = pl->Ka;
     j.model = pl->model;
     j.amp_lstride = (pl->model & RS_MODEL_BLOCK_STRENGTH) ? px->P : 0;
     j.M = pl->M;
@@ -314,6 +315,7 @@ static rs_status plan_common(const rs_radar *r, rs_form form, rs_dtype dtype, in
     pl->Kd = ((2.0 * r->fc) * r->Tb) / r->c0;
     pl->Kf = (2.0 * r->fc) / (r->c0 * r->Fs);
     pl->Krvp = (2.0 * r->mu) / (r->c0 * r->c0);
+    pl->Ka = (2.0 * r->fc) / r->c0;
     pl->model = r->model;
     pl->form = form;
     pl->dtype = dtype;

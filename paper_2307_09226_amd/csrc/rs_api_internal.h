@@ -10,6 +10,7 @@ struct rs_plan {
     double fc = 0, mu = 0, Fs = 0, Tb = 0, c0 = 0;
     double Kc = 0, Kb = 0, Kd = 0;  // binary64 phase constants
     double Kf = 0, Krvp = 0;        // ... of the intra-chirp Doppler and video-phase variants
+    double Ka = 0;                  // 2 fc / c0, the far-field angle term (not switched by carrier)
     int32_t model = 0;              // rs_model_flags
     double *d_ant = nullptr;        // device tx[M][3] then rx[N][3]
     rs_form form = RS_FORM_MFMA_SPLIT16;

@@ -35,28 +35,32 @@ __device__ __forceinline__ double rs_frac(double v) { return v - __builtin_floor
 // eq. (1)): psi the carrier phase of sigma (cycles, not reduced), b the beat
 // frequency (cycles per fast-time sample), beta the Doppler phase per block
 // (cycles).  Without variant flags R = (|x - tx_m| + |x - rx_r|) / 2,
-// psi = R Kc, b = R Kb, beta = v Kd.  The flags (rs_model_flags) change psi
-// and b in the order below.  J: an rs_job or any struct with its constants
-// (model, M, Kc, Kb, Kd, Kf, Krvp).
+// psi = R Kc, b = R Kb, beta = v Kd.  The far-field flag uses eq. (2)'s
+// range Rp = |x| and angle term instead: psi = Rp Kc - s Ka,
+// s = u.(tx_m + rx_r)/2, u = x / Rp, b = Rp Kb (Ka = 2 fc / c0 even when
+// the carrier phase is off, so that Kc = 0 gives eq. (2) as printed).  The
+// other flags (rs_model_flags) change psi and b in the order below.
+// J: an rs_job or any struct with its constants (model, M, Kc, Kb, Kd, Kf,
+// Krvp, Ka).
 template <typename JobConsts>
 __device__ __forceinline__ void rs_chan_args(const JobConsts &J, float x, float y, float z, float v, int m,
                                              const double *tx, const double *rx, double *psi, double *b,
                                              double *beta)
 {
-    double Rc, Rb;
+    double Rb, ps;
     if (J.model & 1) {  // far field, eq. (2)
         const double xd = (double)x, yd = (double)y, zd = (double)z;
         const double Rp = __builtin_sqrt((xd * xd + yd * yd) + zd * zd);
         const double ux = xd / Rp, uy = yd / Rp, uz = zd / Rp;
         const double s = 0.5 * ((ux * (tx[0] + rx[0]) + uy * (tx[1] + rx[1])) + uz * (tx[2] + rx[2]));
-        Rc = Rp - s;
+        ps = Rp * J.Kc - s * J.Ka;
         Rb = Rp;
     } else {
-        Rc = 0.5 * (rs_distance(x, y, z, tx) + rs_distance(x, y, z, rx));
-        Rb = Rc;
+        Rb = 0.5 * (rs_distance(x, y, z, tx) + rs_distance(x, y, z, rx));
+        ps = Rb * J.Kc;
     }
     *beta = (double)v * J.Kd;
-    *psi = Rc * J.Kc;
+    *psi = ps;
     *b = Rb * J.Kb;
     if (J.model & 8) *psi = *psi - (Rb * Rb) * J.Krvp;                    // residual video phase
     if (J.model & 2) *psi = *psi - *beta * ((double)m / (double)J.M);     // Tx slot timing
@@ -68,7 +72,7 @@ __device__ __forceinline__ void rs_chan_args(const JobConsts &J, float x, float 
 // memory to the compiler, which reloads its fields after every LDS store
 // (they might alias) and waits for each such load.
 struct rs_item_consts {
-    double Kc, Kb, Kd, Kf, Krvp;
+    double Kc, Kb, Kd, Kf, Krvp, Ka;
     double tx[3], rx[3];            // antennas of the item's channel (Tx m, Rx r)
     const float *x, *y, *z, *amp, *vr;
     int64_t amp_lstride;
@@ -82,6 +86,7 @@ __device__ __forceinline__ void rs_item_consts_of(const rs_job &J, int m, int r,
     k.Kd = J.Kd;
     k.Kf = J.Kf;
     k.Krvp = J.Krvp;
+    k.Ka = J.Ka;
     for (int i = 0; i < 3; ++i) {
         k.tx[i] = J.ant[3 * m + i];
         k.rx[i] = J.ant[3 * (J.M + r) + i];

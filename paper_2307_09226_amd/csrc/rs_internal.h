@@ -14,6 +14,7 @@ struct rs_job {
     const double *ant;         // device antenna table: tx[M][3] then rx[N][3]
     double Kc, Kb, Kd;         // phase constants of the binary64 recipe
     double Kf, Krvp;           // constants of the intra-chirp / video-phase variants
+    double Ka;                 // 2 fc / c0 whatever the carrier switch (far-field angle term)
     int32_t M, N, Ns, L;
     int32_t n_tiles, l_tiles;  // output tiles along n and l
     int32_t S, chunk;          // pixel chunks and pixels per chunk

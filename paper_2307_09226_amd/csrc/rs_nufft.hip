@@ -67,7 +67,7 @@ struct nu_args {
     const float *x, *y, *z, *amp, *vr;
     int64_t P;
     const double *ant;          // tx[M][3] then rx[N][3]
-    double Kc, Kb, Kd, Kf, Krvp;
+    double Kc, Kb, Kd, Kf, Krvp, Ka;
     int32_t M, N, Ns, L, model;
     int32_t n1, n2;             // grid size along n and l (powers of two)
     float beta;                 // kernel shape
@@ -916,6 +916,7 @@ rs_status rs_nufft_enqueue(const rs_plan *pl, const rs_pixels *px, void *cube, v
     A.Kd = pl->Kd;
     A.Kf = pl->Kf;
     A.Krvp = pl->Krvp;
+    A.Ka = pl->Ka;
     A.M = pl->M;
     A.N = pl->N;
     A.Ns = pl->Ns;

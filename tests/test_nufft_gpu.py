@@ -68,15 +68,15 @@ def test_against_nufft_oracle_and_exact(name, tol):
     assert rel <= tol + GATE_FP32
 
 
-@pytest.mark.parametrize("model", [15, 1, 2 | 4 | 8])
-def test_variants_and_complex128(model):
-    r = dataclasses.replace(RADARS["ragged"](), model=model)
+@pytest.mark.parametrize("model,carrier", [(15, 1), (1, 1), (1, 0), (2 | 4 | 8, 1)])
+def test_variants_and_complex128(model, carrier):
+    r = dataclasses.replace(RADARS["ragged"](), model=model, carrier_phase=carrier)
     px = scenes.tiny_scene(420 + model, 1500, vmax=6.0)
     got = _synth(r, px, 1e-5, dtype=1, ws=True)
     assert got.dtype == np.complex128
     rel, _ = errors(got, oracle.cube(r, px))
     rel_nu, _ = errors(got, onufft.nufft_cube(r, px, 1e-5))
-    print(f"nufft model={model}: vs exact {rel:.2e}, vs NUFFT oracle {rel_nu:.2e}", flush=True)
+    print(f"nufft model={model} carrier={carrier}: vs exact {rel:.2e}, vs NUFFT oracle {rel_nu:.2e}", flush=True)
     assert rel_nu <= GATE_FP32 and rel <= 1e-5 + GATE_FP32
 
 

@@ -1,5 +1,7 @@
 """Signal-model variants (far field as eq. (2), Tx slot timing, Doppler within
-the chirp, residual video phase) on the GPU against the CPU oracle."""
+the chirp, residual video phase) on the GPU against the CPU oracle.  The far
+field runs both with the carrier phase (its far-field-limit reading) and
+without it (eq. (2) as printed)."""
 import dataclasses
 
 import numpy as np
@@ -11,7 +13,9 @@ from gpu_util import GATE_MFMA, GATE_PLAIN_C128, errors, synth
 
 pytestmark = pytest.mark.gpu
 
-MODELS = [1, 2, 4, 8, 15]
+# (model flags, carrier phase)
+MODELS = [(1, 1), (1, 0), (2, 1), (4, 1), (8, 1), (15, 1), (15, 0)]
+IDS = [f"model{m}-carrier{c}" for m, c in MODELS]
 
 
 def _rs():
@@ -19,32 +23,32 @@ def _rs():
     return rs
 
 
-def _radar(model):
-    r = scenes.radar_for(3, 2, 72, 40, Fs=10e6, Tb=120e-6)
+def _radar(model, carrier=1):
+    r = scenes.radar_for(3, 2, 72, 40, Fs=10e6, Tb=120e-6, carrier_phase=carrier)
     return dataclasses.replace(r, model=model)
 
 
-@pytest.mark.parametrize("model", MODELS)
-def test_plain_c128_full_cube(model):
+@pytest.mark.parametrize("model,carrier", MODELS, ids=IDS)
+def test_plain_c128_full_cube(model, carrier):
     rs = _rs()
-    r = _radar(model)
+    r = _radar(model, carrier)
     px = scenes.tiny_scene(60 + model, 517, vmax=6.0)
     ref = oracle.cube(r, px)
     got = synth(r, px, rs.RS_FORM_FP64_DIRECT, rs.RS_C128)
     rel, mx = errors(got, ref)
-    print(f"plain model={model} relL2={rel:.3e} maxabs={mx:.3e}")
+    print(f"plain model={model} carrier={carrier} relL2={rel:.3e} maxabs={mx:.3e}")
     assert rel <= GATE_PLAIN_C128 and mx <= GATE_PLAIN_C128
 
 
-@pytest.mark.parametrize("model", MODELS)
-def test_mfma_full_cube(model):
+@pytest.mark.parametrize("model,carrier", MODELS, ids=IDS)
+def test_mfma_full_cube(model, carrier):
     rs = _rs()
-    r = _radar(model)
+    r = _radar(model, carrier)
     px = scenes.tiny_scene(70 + model, 2111, vmax=6.0)
     ref = oracle.cube(r, px)
     got = synth(r, px, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64)
     rel, mx = errors(got, ref)
-    print(f"mfma model={model} relL2={rel:.3e} maxabs={mx:.3e}")
+    print(f"mfma model={model} carrier={carrier} relL2={rel:.3e} maxabs={mx:.3e}")
     assert rel <= GATE_MFMA and mx <= GATE_MFMA
 
 
