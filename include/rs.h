@@ -232,7 +232,33 @@ rs_status rs_beat_synthesize(rs_plan *plan, const rs_pixels *pixels, void *cube,
 rs_status rs_beat_synthesize_ws(rs_plan *plan, const rs_pixels *pixels, void *cube,
                                 void *workspace, size_t workspace_bytes, void *hip_stream);
 
-/* Enqueue `nframes` cubes that share one plan (e.g. consecutive animation
+/* Size of the static device array that rs_beat_synthesize_noalloc uses as
+ * its workspace (one array per device, held until the process ends). */
+#define RS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * rs_beat_synthesize with no allocation at all.  The workspace that
+ * rs_beat_synthesize_ws takes from the caller (rs_plan_workspace_bytes) comes
+ * from a static device array of RS_STATIC_SCRATCH_BYTES bytes per device
+ * instead; the kernels and their chunking are those of rs_beat_synthesize,
+ * so the cube is bitwise the same.  The caller still passes the pixels and
+ * the cube.  The array's address is looked up once per device, on the first
+ * call there (hipGetSymbolAddress).  Every call on one device shares that
+ * device's array and nothing in it carries over from call to call (each call
+ * writes every workspace entry it reads), but calls that overlap in time on
+ * one device -- different streams, or threads without ordering -- race on it
+ * and give wrong cubes; calls in order on one stream are safe.  Calls on
+ * different devices use different arrays.
+ * Errors: as rs_beat_synthesize_ws; RS_E_INVALID (nothing launched) when the
+ * plan's workspace for P pixels exceeds RS_STATIC_SCRATCH_BYTES (the
+ * matrix-core plan of a 3 x 4 array with Ns 256 and L 128 needs at most
+ * 63 MiB whatever P, its binary64 plain form twice that, which is refused);
+ * RS_E_UNSUPPORTED for device ordinals >= 64. */
+rs_status rs_beat_synthesize_noalloc(rs_plan *plan, const rs_pixels *pixels, void *cube,
+                                     void *hip_stream);
+
+/* Enqueue `nframes` cubes that share one plan/* Enqueue `nframes` cubes that share one plan (e.g. consecutive animation
  * frames with different pixel counts) as ONE persistent launch over all
  * frames' work items plus one reduction launch (NUFFT plans: the frames'
  * launches one after another on one workspace).  frames: HOST array of

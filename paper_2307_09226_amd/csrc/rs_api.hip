@@ -639,6 +639,65 @@ extern "C" rs_status rs_beat_synthesize(rs_plan *pl, const rs_pixels *px, void *
     return s;
 }
 
+// ------------------------------------------------ allocation-free call ----
+// rs_beat_synthesize_noalloc keeps its workspace (split-K partial sums and
+// chunk scales, or the NUFFT grid) in this file-scope device array, one copy
+// per device the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: the name is a host
+// stand-in, not a device address.  The address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) char scratch[RS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices];
+
+// The device address of `scratch` on `dev`, which the caller has made
+// current.
+rs_status scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return rs_fail(RS_E_UNSUPPORTED, "device %d beyond the %d the static scratch serves", dev,
+                       kMaxScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return rs_fail(RS_E_DEVICE, "hipGetSymbolAddress of the static scratch on device %d: %s", dev,
+                           hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RS_OK;
+}
+
+}  // namespace
+
+extern "C" rs_status rs_beat_synthesize_noalloc(rs_plan *pl, const rs_pixels *px, void *cube, void *stream)
+{
+    if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
+    if (!cube) return rs_fail(RS_E_INVALID, "cube is NULL");
+    rs_status s = rs_check_pixels(pl, px);
+    if (s != RS_OK) return s;
+    size_t need = 0;
+    if ((s = rs_plan_workspace_bytes(pl, px->P, &need)) != RS_OK) return s;
+    if (need > (size_t)RS_STATIC_SCRATCH_BYTES)
+        return rs_fail(RS_E_INVALID,
+                       "workspace of %zu bytes exceeds the static scratch of %zu bytes (P = %lld): use "
+                       "rs_beat_synthesize or rs_beat_synthesize_ws",
+                       need, (size_t)RS_STATIC_SCRATCH_BYTES, (long long)px->P);
+    void *ws = nullptr;
+    {
+        device_guard g(pl->device);
+        if (g.st != RS_OK) return g.st;
+        if ((s = scratch_address(pl->device, &ws)) != RS_OK) return s;
+    }
+    return rs_beat_synthesize_ws(pl, px, cube, ws, (size_t)RS_STATIC_SCRATCH_BYTES, stream);
+}
+
 extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *frames, int32_t nframes,
                                               void *cubes, void *stream)
 {

@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("RS_LIBRARY") or os.path.join(_PKG, "librs.so")
 RS_OK, RS_E_INVALID, RS_E_NOMEM, RS_E_DEVICE, RS_E_UNSUPPORTED, RS_E_BUSY, RS_E_NOT_FOUND = range(7)
 RS_FORM_FP64_DIRECT, RS_FORM_MFMA_SPLIT16, RS_FORM_NUFFT = 0, 1, 2
 RS_C64, RS_C128 = 0, 1
+RS_STATIC_SCRATCH_BYTES = 64 << 20  # include/rs.h: workspace of rs_beat_synthesize_noalloc
 RS_REQ_QUEUED, RS_REQ_RUNNING, RS_REQ_DONE, RS_REQ_FAILED, RS_REQ_CANCELLED = range(5)
 RS_MODEL_FAR_FIELD, RS_MODEL_TDM_SLOT, RS_MODEL_INTRA_CHIRP, RS_MODEL_RVP, RS_MODEL_BLOCK_STRENGTH = 1, 2, 4, 8, 16
 STATUS_NAMES = {0: "RS_OK", 1: "RS_E_INVALID", 2: "RS_E_NOMEM", 3: "RS_E_DEVICE",
@@ -101,6 +102,7 @@ SIGNATURES = {
     "rs_beat_synthesize": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP]),
     "rs_beat_synthesize_ws": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP,
                                              ctypes.c_size_t, _VP]),
+    "rs_beat_synthesize_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP]),
     "rs_beat_synthesize_batch": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), ctypes.c_int32,
                                                 _VP, _VP]),
     "rs_plan_destroy": (None, [_VP]),
@@ -315,6 +317,14 @@ def rs_beat_synthesize_ws(plan: Plan, pixels: DevicePixels, cube, workspace, str
     _check(lib.rs_beat_synthesize_ws(plan.handle, ctypes.byref(ps), _ptr(cube),
                                      _ptr(workspace) if nbytes else None, nbytes,
                                      _stream_handle(stream)))
+    return cube
+
+
+def rs_beat_synthesize_noalloc(plan: Plan, pixels: DevicePixels, cube, stream=None):
+    """rs_beat_synthesize with the library's static device scratch as its
+    workspace: nothing is allocated (see include/rs.h)."""
+    ps = pixels.struct(plan)
+    _check(lib.rs_beat_synthesize_noalloc(plan.handle, ctypes.byref(ps), _ptr(cube), _stream_handle(stream)))
     return cube
 
 
