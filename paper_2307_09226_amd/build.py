@@ -55,6 +55,21 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     return LIB
 
 
+TEST_PRIMS_SRC = os.path.join(ROOT, "tests", "csrc", "rs_prims.hip")
+TEST_PRIMS_LIB = os.path.join(ROOT, "tests", "csrc", "librs_prims.so")
+
+
+def build_test_prims(verbose: bool = False) -> str:
+    """Compile the test-only primitive library (tests/csrc) with the
+    library's own flags; returns its path."""
+    out_tmp = TEST_PRIMS_LIB + ".tmp"
+    _run([HIPCC, *FLAGS, "-shared", TEST_PRIMS_SRC, "-o", out_tmp])
+    os.replace(out_tmp, TEST_PRIMS_LIB)
+    if verbose:
+        print("built", TEST_PRIMS_LIB, file=sys.stderr)
+    return TEST_PRIMS_LIB
+
+
 def device_asm(src: str) -> str:
     """Device assembly of one source (for inspection of the generated code)."""
     with tempfile.TemporaryDirectory(prefix="rs_asm_") as tmp:

@@ -49,6 +49,7 @@
 // and reloaded by the next segment, which makes the result independent of
 // how a chunk is split into segments.
 #include "rs_device.h"
+#include "rs_split16.h"
 
 #include <cstdlib>
 #include <mutex>
@@ -57,7 +58,6 @@
 namespace {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kKP = 16;        // pixels per step (two K=16 matrix steps)
@@ -76,42 +76,13 @@ struct __align__(16) pix_par {
     float pad_;
 };
 
-// frac in binary64 (v_fract_f64: v - floor(v), held below 1), then binary32
-__device__ __forceinline__ float frac32(double v) { return (float)__builtin_amdgcn_fract(v); }
-
-// hi = rne16(x) for a pair, packed in one register (v_cvt_pk_f16_f32)
-__device__ __forceinline__ half2v hi2(float x, float y) { return half2v{(_Float16)x, (_Float16)y}; }
-
-// lo = rne16(x - hi): x - hi is exact in fp32, so the mixed-precision
-// multiply-add -hi * 1 + x rounded once to fp16 gives it, one instruction per
-// component (v_fma_mixlo_f16 writes bits 15:0, v_fma_mixhi_f16 bits 31:16;
-// op_sel_hi marks the fp16 source, op_sel picks its half).
-__device__ __forceinline__ half2v lo2(float x, float y, half2v h)
-{
-    const unsigned hb = __builtin_bit_cast(unsigned, h);
-    unsigned r;
-    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hb), "v"(x));
-    asm("v_fma_mixhi_f16 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(r) : "v"(hb), "v"(y));
-    return __builtin_bit_cast(half2v, r);
-}
-
-__device__ __forceinline__ unsigned bits(half2v v) { return __builtin_bit_cast(unsigned, v); }
-
-// Pins a binary32 value: the empty asm statement hides how it was produced,
-// so the compiler cannot fuse a later fp16 conversion with the multiply-add
-// that produced it (that would round the exact result once, to fp16).  Every
-// code path then yields the same bits for the same phasor, which keeps a
-// cube independent of how its steps were split over launches.
-__device__ __forceinline__ void pin(float &u, float &w) { asm("" : "+v"(u), "+v"(w)); }
-
-// (u + j w) * (rx + j ry) in binary32
-__device__ __forceinline__ void rot(float &u, float &w, float rx, float ry)
-{
-    float un = __builtin_fmaf(u, rx, -(w * ry));
-    w = __builtin_fmaf(u, ry, w * rx);
-    u = un;
-    pin(u, w);
-}
+typedef rs_half2v half2v;
+__device__ __forceinline__ float frac32(double v) { return rs_frac32(v); }
+__device__ __forceinline__ half2v hi2(float x, float y) { return rs_hi2(x, y); }
+__device__ __forceinline__ half2v lo2(float x, float y, half2v h) { return rs_lo2(x, y, h); }
+__device__ __forceinline__ unsigned bits(half2v v) { return rs_bits(v); }
+__device__ __forceinline__ void pin(float &u, float &w) { rs_pin(u, w); }
+__device__ __forceinline__ void rot(float &u, float &w, float rx, float ry) { rs_rot(u, w, rx, ry); }
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 

@@ -20,6 +20,25 @@ def errors(got, ref):
     return rel, mx
 
 
+def marginal_ratio(cube, ref_marginal, axis):
+    """The cube's error seen through a closed-form marginal.  Summing the
+    cube over `axis` (2: fast time, 1: slow time, n entries per row) turns an
+    error dY into dM with ||dM||_2 <= sqrt(n) ||dY||_2 and
+    max |dM| <= n max |dY| (Cauchy-Schwarz), so a cube within relative L2
+    error g and max-abs error g (relative to its largest entry) gives
+    max(||dM||_2 / (sqrt(n) ||Y||_2), max |dM| / (n max |Y|)) <= g; this
+    returns that maximum, to be held to the cube's gate.  (A plain relative
+    error of the marginal is not implied by the gates: where the pixels'
+    phases cancel over a row the marginal is far smaller than the row, and
+    the entries' rounding, which does not cancel, dominates it.)"""
+    cube = np.asarray(cube, dtype=np.complex128)
+    d = cube.sum(axis=axis) - np.asarray(ref_marginal)
+    n = cube.shape[axis]
+    l2 = np.linalg.norm(d.ravel()) / max(np.sqrt(n) * np.linalg.norm(cube.ravel()), 1e-300)
+    mx = np.max(np.abs(d)) / max(n * np.max(np.abs(cube)), 1e-300)
+    return float(max(l2, mx))
+
+
 def synth(radar, px, form, dtype, device="cuda:0", max_pixels=None, ws=False):
     import torch
     from paper_2307_09226_amd import rs
