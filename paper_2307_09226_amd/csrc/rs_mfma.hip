@@ -23,8 +23,13 @@
 //           the next step's phasors are computed while the matrix cores run)
 //   D     = B operand, evaluated once per workgroup per 16-pixel step into
 //           double-buffered LDS (both column arrangements, hi and lo)
-// With two waves per SIMD (NW = 8) the hardware interleaves one wave's
-// matrix instructions with the other's phasor arithmetic.
+// Two step schedules.  Phase-shifted waves (NW = 8): the two waves of a SIMD
+// run their matrix and vector parts in opposite order, so the hardware
+// interleaves one wave's matrix instructions with the other's phasor
+// arithmetic.  Software-pipelined interleave (the other shapes, and NW = 8
+// when the plan turns the phase shift off): every wave alternates one matrix
+// group with one slice of vector work, the phasor evaluation cut into stages
+// one slice apart so that no wave waits on its own vector results.
 // Phasor cost: per pixel and lane one binary64-reduced phasor; the other rows
 // of the lane follow by binary32 rotation with exp(j2pi frac(32 b)), and the
 // slow-time phasors of a thread by rotation with exp(j2pi frac(16 beta)) --
@@ -83,6 +88,16 @@ __device__ __forceinline__ half2v lo2(float x, float y, half2v h) { return rs_lo
 __device__ __forceinline__ unsigned bits(half2v v) { return rs_bits(v); }
 __device__ __forceinline__ void pin(float &u, float &w) { rs_pin(u, w); }
 __device__ __forceinline__ void rot(float &u, float &w, float rx, float ry) { rs_rot(u, w, rx, ry); }
+
+// Both column arrangements of a D entry u + j w, real (u, w) and imaginary
+// (-w, u), each split into hi and lo.
+__device__ __forceinline__ void d_split(float u, float w, half2v &hre, half2v &him, half2v &lre, half2v &lim)
+{
+    hre = hi2(u, w);
+    him = hi2(-w, u);
+    lre = lo2(u, w, hre);
+    lim = lo2(-w, u, him);
+}
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
@@ -222,8 +237,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             for (int k = 0; k < DPT; ++k) {
                 float su = u, sw = w;
                 if constexpr (BS) scaled(u, w, al[k], su, sw);
-                const half2v hre = hi2(su, sw), him = hi2(-sw, su);
-                const half2v lre = lo2(su, sw, hre), lim = lo2(-sw, su, him);
+                half2v hre, him, lre, lim;
+                d_split(su, sw, hre, him, lre, lim);
                 const int cre = d_column(k) * kCS, cim = cre + 32 * kCS;
                 *reinterpret_cast<unsigned *>(dh + cre) = bits(hre);
                 *reinterpret_cast<unsigned *>(dh + cim) = bits(him);
@@ -300,9 +315,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         // the other evaluates phasors.  The first wave evaluates F of the
         // next step after its products, the second F of the current step
         // before them; either way the F registers are dead when they are
-        // rewritten, so one set suffices.
-        //   Otherwise the vector slices are interleaved with the groups and F
-        // is double-buffered.
+        // rewritten, so one set suffices.  (Without the phase shift the
+        // steps run step_pipe below.)
         // What is evaluated after the last step is never used.
         constexpr int NG = 2 * CB;                  // groups per step
         constexpr int FG = NG - DPT;                // slices evaluating F
@@ -355,8 +369,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 if (gi < DPT) {
                     float su = u, sw = w;
                     if constexpr (BS) scaled(u, w, al[gi], su, sw);
-                    const half2v hre = hi2(su, sw), him = hi2(-sw, su);
-                    const half2v lre = lo2(su, sw, hre), lim = lo2(-sw, su, him);
+                    half2v hre, him, lre, lim;
+                    d_split(su, sw, hre, him, lre, lim);
                     const int cre = d_column(gi) * kCS, cim = cre + 32 * kCS;
                     *reinterpret_cast<unsigned *>(dwh + cre) = bits(hre);
                     *reinterpret_cast<unsigned *>(dwh + cim) = bits(him);
@@ -371,7 +385,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                     }
                 }
             };
-            if (kShift && wave >= 4) {
+            if (wave >= 4) {
                 // second wave of each SIMD: phasor work first, then the
                 // matrix work, so that it complements the first wave (with
                 // strengths per block the F slices go first, giving the
@@ -385,7 +399,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                     mfma_group(gi);
                     __builtin_amdgcn_sched_barrier(0);
                 }
-            } else if (kShift) {
+            } else {
                 mfma_prologue();
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
@@ -394,14 +408,131 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 }
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) valu_slice(gi);
-            } else {
-                mfma_prologue();
+            }
+            __syncthreads();
+        };
+
+        // Software-pipelined interleave (no phase shift): every wave runs the
+        // same stream, one matrix group then one vector slice.  The vector
+        // work of the next step is cut into stages -- the pixel parameters
+        // read from LDS, the binary64 phase, the sin / cos, the split and the
+        // store -- and each stage sits one slice after the one producing its
+        // operands, so that a wave never waits on its own vector results and
+        // the matrix instructions of the two waves of a SIMD keep the matrix
+        // core busy.  F pixel fp starts in slice f_slot(fp) and D entry k is
+        // split and stored in slice d_slot(k); the phasors and their bits are
+        // those of gen_f_pixel and gen_d.
+        auto step_pipe = [&](int st, auto cur, auto nxt, const fops &fc, fops &fn) {
+            if ((st % kSPB) == 0 && st / kSPB + 1 < nblocks) load_block(st / kSPB + 1);
+            const int s1 = st + 1;
+            const pix_par *ps1 = &sPar[(s1 / kSPB) & 1][(s1 % kSPB) * kKP];
+            float al[DPT];
+            if constexpr (BS) load_al(s1, al);
+            char (&dbn)[2][DBYTES] = decltype(nxt)::value ? sD1 : sD0;
+            char *dwh = dbn[0] + lq * kCS + q * 4;
+            char *dwl = dbn[1] + lq * kCS + q * 4;
+            int lo = li * kCS + 16 * g;
+            asm volatile("" : "+v"(lo));
+            const char (&dbc)[2][DBYTES] = decltype(cur)::value ? sD1 : sD0;
+            const char *drh = dbc[0] + lo;
+            const char *drl = dbc[1] + lo;
+            constexpr int kBD = 1;
+            auto boff = [](int gi) { return (gi % CB) * 32 * kCS + 32 * (gi / CB); };
+            half8 bh[kBD + 1], bl[kBD + 1];
+            auto load_b = [&](int gi) {
+                bh[gi % (kBD + 1)] = *reinterpret_cast<const half8 *>(drh + boff(gi));
+                bl[gi % (kBD + 1)] = *reinterpret_cast<const half8 *>(drl + boff(gi));
+            };
+            auto mfma_group = [&](int gi) {
+                if (gi + kBD < NG) load_b(gi + kBD);
+                const int t = gi / CB, cb = gi % CB;
+                const half8 h = bh[gi % (kBD + 1)], l = bl[gi % (kBD + 1)];
 #pragma unroll
-                for (int gi = 0; gi < NG; ++gi) {
-                    mfma_group(gi);
-                    valu_slice(gi);
-                    __builtin_amdgcn_sched_barrier(0);
+                for (int rb = 0; rb < RB; ++rb) {
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], h, acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.h[t][rb], l, acc[rb][cb], 0, 0, 0);
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(fc.l[t][rb], h, acc[rb][cb], 0, 0, 0);
                 }
+            };
+            static_assert(NG >= 8, "the pipelined schedule needs 8 slices");
+            // stage registers (indices are compile-time: registers, live only
+            // between their stages)
+            double dbeta = 0.0;
+            float da = 0.f, dcx = 0.f, dcy = 0.f, dfr = 0.f, u = 0.f, w = 0.f;
+            double fpsi[8], fbb[8];
+            float fex[8], fey[8], fph[8], fcv[8], fsv[8];
+            auto f_slot = [](int fp) { return (fp * (NG - 3)) / 8; };
+            auto d_slot = [](int k) { return 3 + (k * (NG - 4)) / DPT; };
+            auto slice = [&](int gi) {
+                // D: parameters, binary64 phase, sin / cos, then the entries
+                if (gi == 0) {
+                    const pix_par &pd = ps1[q];
+                    dbeta = pd.beta;
+                    da = pd.a;
+                    dcx = pd.srx;
+                    dcy = pd.sry;
+                }
+                if (gi == 1) dfr = frac32(dbeta * (double)(l0 + lq));
+                if (gi == 2) {
+                    u = da * __builtin_amdgcn_cosf(dfr);
+                    w = da * __builtin_amdgcn_sinf(dfr);
+                    pin(u, w);
+                }
+#pragma unroll
+                for (int k = 0; k < DPT; ++k) {
+                    if (gi != d_slot(k)) continue;
+                    float su = u, sw = w;
+                    if constexpr (BS) scaled(u, w, al[k], su, sw);
+                    half2v hre, him, lre, lim;
+                    d_split(su, sw, hre, him, lre, lim);
+                    const int cre = d_column(k) * kCS, cim = cre + 32 * kCS;
+                    *reinterpret_cast<unsigned *>(dwh + cre) = bits(hre);
+                    *reinterpret_cast<unsigned *>(dwh + cim) = bits(him);
+                    *reinterpret_cast<unsigned *>(dwl + cre) = bits(lre);
+                    *reinterpret_cast<unsigned *>(dwl + cim) = bits(lim);
+                    if (k + 1 < DPT) rot(u, w, dcx, dcy);
+                }
+                // F of step s1: stages of earlier pixels first
+#pragma unroll
+                for (int fp = 0; fp < 8; ++fp) {
+                    const int s0 = f_slot(fp), ft = fp >> 2, j = fp & 3;
+                    if (gi == s0 + 3) {
+                        float cv = fcv[fp], sv = fsv[fp];
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb) {
+                            const half2v h = hi2(cv, sv);
+                            u32x4 vh = __builtin_bit_cast(u32x4, fn.h[ft][rb]);
+                            u32x4 vl = __builtin_bit_cast(u32x4, fn.l[ft][rb]);
+                            vh[j] = bits(h);
+                            vl[j] = bits(lo2(cv, sv, h));
+                            fn.h[ft][rb] = __builtin_bit_cast(half8, vh);
+                            fn.l[ft][rb] = __builtin_bit_cast(half8, vl);
+                            if (rb + 1 < RB) rot(cv, sv, fex[fp], fey[fp]);
+                        }
+                    }
+                    if (gi == s0 + 2) {
+                        fcv[fp] = __builtin_amdgcn_cosf(fph[fp]);
+                        fsv[fp] = __builtin_amdgcn_sinf(fph[fp]);
+                    }
+                    if (gi == s0 + 1) fph[fp] = frac32(__builtin_fma(fbb[fp], nrow0, fpsi[fp]));
+                    if (gi == s0) {
+                        const pix_par &pf = ps1[8 * ft + 4 * g + j];
+                        fpsi[fp] = pf.psi_f;
+                        fbb[fp] = pf.b;
+                        if constexpr (RB > 1) {
+                            fex[fp] = pf.e32x;
+                            fey[fp] = pf.e32y;
+                        }
+                    }
+                }
+            };
+#pragma unroll
+            for (int gi = 0; gi < kBD; ++gi) load_b(gi);
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                mfma_group(gi);
+                slice(gi);
+                __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
         };
@@ -426,9 +557,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             }
         } else {
             for (int st = k0; st < k1; st += 2) {
-                step(st, buf0_t{}, buf1_t{}, fa, fb, st + 1);
+                step_pipe(st, buf0_t{}, buf1_t{}, fa, fb);
                 if (st + 1 >= k1) break;
-                step(st + 1, buf1_t{}, buf0_t{}, fb, fa, st + 2);
+                step_pipe(st + 1, buf1_t{}, buf0_t{}, fb, fa);
             }
         }
 

@@ -12,10 +12,19 @@ __device__ __forceinline__ float rs_frac32(double v) { return (float)__builtin_a
 // hi = rne16(x) for a pair, packed in one register (v_cvt_pk_f16_f32)
 __device__ __forceinline__ rs_half2v rs_hi2(float x, float y) { return rs_half2v{(_Float16)x, (_Float16)y}; }
 
+// Pins a binary32 value: the empty asm statement hides how it was produced,
+// so the compiler cannot fuse a later fp16 conversion with the multiply-add
+// that produced it (that would round the exact result once, to fp16).  Every
+// code path then yields the same bits for the same phasor, which keeps a
+// cube independent of how its steps were split over launches.
+__device__ __forceinline__ void rs_pin(float &u, float &w) { asm("" : "+v"(u), "+v"(w)); }
+
 // lo = rne16(x - hi): x - hi is exact in fp32, so the mixed-precision
 // multiply-add -hi * 1 + x rounded once to fp16 gives it, one instruction per
 // component (v_fma_mixlo_f16 writes bits 15:0, v_fma_mixhi_f16 bits 31:16;
-// op_sel_hi marks the fp16 source, op_sel picks its half).
+// op_sel_hi marks the fp16 source, op_sel picks its half).  (Widening hi with
+// v_cvt_f32_f16 and subtracting in binary32 gives the same bits but measured
+// slower in the matrix-core kernel.)
 __device__ __forceinline__ rs_half2v rs_lo2(float x, float y, rs_half2v h)
 {
     const unsigned hb = __builtin_bit_cast(unsigned, h);
@@ -26,13 +35,6 @@ __device__ __forceinline__ rs_half2v rs_lo2(float x, float y, rs_half2v h)
 }
 
 __device__ __forceinline__ unsigned rs_bits(rs_half2v v) { return __builtin_bit_cast(unsigned, v); }
-
-// Pins a binary32 value: the empty asm statement hides how it was produced,
-// so the compiler cannot fuse a later fp16 conversion with the multiply-add
-// that produced it (that would round the exact result once, to fp16).  Every
-// code path then yields the same bits for the same phasor, which keeps a
-// cube independent of how its steps were split over launches.
-__device__ __forceinline__ void rs_pin(float &u, float &w) { asm("" : "+v"(u), "+v"(w)); }
 
 // (u + j w) * (rx + j ry) in binary32
 __device__ __forceinline__ void rs_rot(float &u, float &w, float rx, float ry)
