@@ -60,6 +60,12 @@ def measured_traffic():
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
 
+def tile_of(desc):
+    """Tile configuration string of a matrix-core plan description."""
+    pipe = desc["waves"] == 8 and desc.get("schedule") == "pipelined"
+    return f"{desc['wave_rows']}x{desc['tile_l']}x{desc['waves']}" + ("i" if pipe else "")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +190,10 @@ def main():
     # ---- headline: split-fp16 matrix-core form ---------------------------------
     plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=px.P)
     cube = rs.new_cube(plan, dev)
+    # the plan's tile configuration is tuned on the frame itself (every built
+    # configuration, 1 + 3 syntheses each), as a user tuning a plan would
+    rule_tile = tile_of(json.loads(plan.describe(px.P)))
+    tuned_tile = rs.rs_plan_tune(plan, dpx, cube, reps=3)
     # the caller keeps the workspace (the allocating call adds a stream-ordered
     # allocation and release per step, ~6 us)
     wsp = torch.empty(max(plan.workspace_bytes(px.P), 1), dtype=torch.uint8, device=dev)
@@ -209,7 +219,8 @@ def main():
                                "Ns=256, L=128, Fs=10 MHz, Tb=3x40 us, complex64 cube",
                    "form": "mfma_split16", "P": px.P, "M": radar.M, "N": radar.N,
                    "Ns": radar.Ns, "L": radar.L, "terms_per_step": terms,
-                   "plan": json.loads(plan.describe(px.P))},
+                   "plan": json.loads(plan.describe(px.P)), "tile_tuned": tuned_tile,
+                   "tile_rule": rule_tile},
         "p50_ms": pct(per, 50), "p99_ms": pct(per, 99),
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP16 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP16, "traffic": measured_traffic(),
@@ -316,18 +327,33 @@ def main():
         dfr = [rs.DevicePixels.from_host(f, dev) for f in frames]
         cubes = rs.new_cube(bplan, dev, count=len(frames))
         bterms = sum(f.P for f in frames) * brad.C * brad.Ns * brad.L
-        with timer:
-            bwall, bper = timed_steps(lambda: rs.rs_beat_synthesize_batch(bplan, dfr, cubes), 3, 1)
-        bk = timer.read()
-        torch.cuda.synchronize()
+        big = int(np.argmax([f.P for f in frames]))
+
+        def batch_run():
+            with timer:
+                bwall, _ = timed_steps(lambda: rs.rs_beat_synthesize_batch(bplan, dfr, cubes), 3, 1)
+            bk = timer.read()
+            torch.cuda.synchronize()
+            return bwall * 1e3 / 3, float(np.mean(bk[1:])) if len(bk) > 1 else None
+
+        # the rule's tile, then the tile tuned on the largest frame through a
+        # tile cache (a fresh file: every run tunes)
+        b_rule_tile = tile_of(json.loads(bplan.describe(frames[big].P)))
+        b_rule_ms, b_rule_k = batch_run()
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            b_tile = rs.rs_plan_tune_cached(bplan, dfr[big], cubes[big], os.path.join(td, "tiles.txt"), reps=2)
+        bms, bkms = batch_run()
         out["batch"] = {
             "workload": "64 animation frames, 3 Tx x 4 Rx, Ns=256, L=64, one persistent launch",
             "pixels_min": min(f.P for f in frames), "pixels_max": max(f.P for f in frames),
             "pixels_total": sum(f.P for f in frames), "terms": bterms,
-            "ms": bwall * 1e3 / 3, "terms_per_s": bterms / (bwall / 3),
-            "kernel_ms": float(np.mean(bk[1:])) if len(bk) > 1 else None,
-            "mfma_frac": (FLOP_MFMA * bterms / (np.mean(bk[1:]) * 1e-3)) / PEAK_FP16 if len(bk) > 1 else None,
+            "tile": b_tile, "tile_tuned_on": f"largest frame ({frames[big].P} pixels), rs_plan_tune_cached",
+            "ms": bms, "terms_per_s": bterms / (bms * 1e-3), "kernel_ms": bkms,
+            "mfma_frac": (FLOP_MFMA * bterms / (bkms * 1e-3)) / PEAK_FP16 if bkms else None,
+            "rule_tile": b_rule_tile, "rule_ms": b_rule_ms, "rule_kernel_ms": b_rule_k,
             "parity_frame0": parity_sampled(brad, frames[0], cubes[0].cpu().numpy(), k=128),
+            "parity_largest": parity_sampled(brad, frames[big], cubes[big].cpu().numpy(), k=128),
         }
         del cubes, dfr
         bplan.close()

@@ -185,31 +185,49 @@ rs_status rs_cube_plan_nufft(const rs_radar *radar, rs_dtype dtype, int64_t max_
  * (0 <= P <= max_pixels).  Errors: RS_E_INVALID. */
 rs_status rs_plan_workspace_bytes(const rs_plan *plan, int64_t P, size_t *bytes);
 
-/* Chooses the matrix-core tile of `plan` by measurement: every tile shape
- * built into the library (rows per wave x columns x waves: 64x128x4,
- * 32x128x4, 32x128x8, 32x64x4, 32x64x8, 64x64x4, 64x64x8, 128x64x4)
- * synthesises `pixels` into `cube` once to warm up and `reps` times timed
- * with HIP events on `hip_stream`, and the shape with the smallest mean time
- * is kept (the plan's own choice otherwise comes from a rule measured on the
- * frame and batch workloads).  The call synchronises the stream and leaves
- * the last synthesis in `cube`.  It changes the plan: call it before the
- * plan is shared, never while other calls use it.  Plans of the other forms
- * are left unchanged.  chosen (may be NULL) receives "WNxTLxNW" (an empty
- * string for the other forms).
+/* Matrix-core tile configurations are named "WNxTLxNW" -- rows per wave x
+ * columns (l) x waves per workgroup; the library builds 64x128x4, 32x128x4,
+ * 32x128x8, 32x64x4, 32x64x8, 64x64x4, 64x64x8 and 128x64x4 -- with an
+ * optional suffix 'i' on the 8-wave shapes.  8-wave shapes run two waves
+ * per SIMD with their matrix and vector work phase-shifted against each
+ * other; with 'i' they run the software-pipelined interleave (each wave
+ * alternates matrix groups with staged slices of phasor work), which the
+ * 4-wave shapes always run (the suffix is accepted there and changes
+ * nothing).  The two schedules of a shape give the same cube bit for bit;
+ * different shapes chunk the pixels differently and so differ in the last
+ * bits, all within the form's error. */
+
+/* Sets the matrix-core tile configuration of `plan` (see above).  It changes
+ * the plan: call it before the plan is shared, never while other calls use
+ * it.  Errors: RS_E_INVALID (NULL plan, or a string that is not a built
+ * configuration), RS_E_UNSUPPORTED (plans of the other forms). */
+rs_status rs_plan_set_tile(rs_plan *plan, const char *tile);
+
+/* Chooses the matrix-core tile configuration of `plan` by measurement:
+ * every built configuration (the eight shapes, and the three 8-wave shapes
+ * again with 'i') synthesises `pixels` into `cube` once to warm up and
+ * `reps` times timed with HIP events on `hip_stream`, and the one with the
+ * smallest mean time is kept (the plan's own choice otherwise comes from a
+ * rule measured on the frame and batch workloads).  The call synchronises
+ * the stream and leaves the last synthesis in `cube`.  It changes the plan:
+ * call it before the plan is shared, never while other calls use it.  Plans
+ * of the other forms are left unchanged.  chosen (may be NULL) receives the
+ * configuration string (an empty string for the other forms).
  * Errors: as rs_beat_synthesize, RS_E_INVALID for reps < 1. */
 rs_status rs_plan_tune(rs_plan *plan, const rs_pixels *pixels, void *cube, int32_t reps,
                        void *hip_stream, char *chosen, size_t chosen_len);
 
 /* rs_plan_tune with a persistent cache of its choices: a text file at
- * cache_path (host path), one entry per line "C Ns L Pb WNxTLxNW" keyed by
- * the channel count, N_s, L and Pb, the pixel count rounded up to a power of
- * two.  On a hit (the last well-formed line with the plan's key and a shape
- * built into the library) the plan takes that shape and nothing is
- * launched; on a miss the shape is tuned as rs_plan_tune does (the cube is
- * synthesised) and the entry appended with one write.  A missing file is
- * an empty cache; lines that do not parse are skipped.  Concurrent callers
- * may both tune and both append; the later line wins.  Plans of the other
- * forms are left unchanged (chosen: empty string, no file access).
+ * cache_path (host path), one entry per line "C Ns L Pb TILE" keyed by the
+ * channel count, N_s, L and Pb, the pixel count rounded up to a power of
+ * two, TILE a configuration string as above.  On a hit (the last
+ * well-formed line with the plan's key and a built configuration) the plan
+ * takes that configuration and nothing is launched; on a miss the
+ * configuration is tuned as rs_plan_tune does (the cube is synthesised) and
+ * the entry appended with one write.  A missing file is an empty cache;
+ * lines that do not parse are skipped.  Concurrent callers may both tune
+ * and both append; the later line wins.  Plans of the other forms are left
+ * unchanged (chosen: empty string, no file access).
  * Errors: as rs_plan_tune, RS_E_INVALID for a NULL cache_path; a file that
  * exists but cannot be read or appended to gives RS_E_INVALID. */
 rs_status rs_plan_tune_cached(rs_plan *plan, const rs_pixels *pixels, void *cube, int32_t reps,

@@ -203,7 +203,7 @@ rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, bool block_stren
     if (pl->form == RS_FORM_FP64_DIRECT)
         rs_launch_plain(L, pl->tl, grid, st);
     else
-        rs_launch_mfma(L, pl->wn, pl->tl, pl->nw, block_strength, grid, st);
+        rs_launch_mfma(L, pl->wn, pl->tl, pl->nw, pl->interleave != 0, block_strength, grid, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "main kernel launch: %s", hipGetErrorString(e));
     if (timed) {
@@ -385,19 +385,10 @@ void rs_choose_tiles(rs_plan *pl)
             nw = 4;
             wn = pl->Ns > 128 ? 64 : 32;
         }
-        // tuning override "WNxTLxNW", e.g. RS_MFMA_TILE=64x128x4
-        if (const char *ov = std::getenv("RS_MFMA_TILE")) {
-            int a = 0, b = 0, c = 4;
-            const int k = std::sscanf(ov, "%dx%dx%d", &a, &b, &c);
-            if (k >= 2 && rs_mfma_shape_supported(a, b, c)) {
-                wn = a;
-                tl = b;
-                nw = c;
-            }
-        }
         pl->wn = wn;
         pl->tl = tl;
         pl->nw = nw;
+        pl->interleave = 0;
         pl->tn = nw * wn;
         pl->items_target = pl->ncu;
         pl->min_chunk = 1024;
@@ -453,24 +444,65 @@ extern "C" rs_status rs_plan_describe(const rs_plan *pl, int64_t P, char *buf, s
     snprintf(buf, len,
              "{\"form\": \"%s\", \"dtype\": \"%s\", \"C\": %d, \"Ns\": %d, \"L\": %d, "
              "\"tile_n\": %d, \"tile_l\": %d, \"wave_rows\": %d, \"waves\": %d, \"n_tiles\": %d, \"l_tiles\": %d, "
-             "\"chunks\": %d, \"chunk_pixels\": %d, \"items\": %lld, \"cus\": %d, \"model\": %d}",
+             "\"schedule\": \"%s\", \"chunks\": %d, \"chunk_pixels\": %d, \"items\": %lld, \"cus\": %d, "
+             "\"model\": %d}",
              pl->form == RS_FORM_FP64_DIRECT ? "fp64_direct" : "mfma_split16",
              pl->dtype == RS_C128 ? "complex128" : "complex64", pl->C, pl->Ns, pl->L, pl->tn,
-             pl->tl, pl->wn, pl->form == RS_FORM_FP64_DIRECT ? 4 : pl->nw, pl->n_tiles, pl->l_tiles, S, chunk,
-             (long long)S * pl->C * pl->n_tiles * pl->l_tiles, pl->ncu, pl->model);
+             pl->tl, pl->wn, pl->form == RS_FORM_FP64_DIRECT ? 4 : pl->nw, pl->n_tiles, pl->l_tiles,
+             pl->form == RS_FORM_FP64_DIRECT ? "lds_blocks"
+                                              : (pl->nw == 8 && !pl->interleave ? "phase_shifted" : "pipelined"),
+             S, chunk, (long long)S * pl->C * pl->n_tiles * pl->l_tiles, pl->ncu, pl->model);
     return RS_OK;
 }
 
 // ----------------------------------------------------------- tile tuning ----
 
-static void set_mfma_shape(rs_plan *pl, int wn, int tl, int nw)
+static void set_mfma_shape(rs_plan *pl, int wn, int tl, int nw, int interleave)
 {
     pl->wn = wn;
     pl->tl = tl;
     pl->nw = nw;
+    pl->interleave = nw == 8 ? interleave : 0;
     pl->tn = nw * wn;
     pl->n_tiles = (pl->Ns + pl->tn - 1) / pl->tn;
     pl->l_tiles = (pl->L + pl->tl - 1) / pl->tl;
+}
+
+// Tile configurations as text: "WNxTLxNW" (rows per wave x columns x
+// waves), with an 'i' suffix for the software-pipelined schedule on 8-wave
+// shapes, which otherwise run phase-shifted waves (4-wave shapes always run
+// the pipelined schedule and take the suffix without effect).
+static bool parse_tile(const char *s, int *wn, int *tl, int *nw, int *il)
+{
+    int a = 0, b = 0, c = 0, n = 0;
+    if (!s || std::sscanf(s, "%dx%dx%d%n", &a, &b, &c, &n) != 3) return false;
+    int i = 0;
+    if (s[n] == 'i') {
+        i = 1;
+        ++n;
+    }
+    if (s[n] != '\0' || !rs_mfma_shape_supported(a, b, c)) return false;
+    *wn = a;
+    *tl = b;
+    *nw = c;
+    *il = c == 8 ? i : 0;
+    return true;
+}
+
+static void format_tile(const rs_plan *pl, char *buf, size_t len)
+{
+    snprintf(buf, len, "%dx%dx%d%s", pl->wn, pl->tl, pl->nw, pl->nw == 8 && pl->interleave ? "i" : "");
+}
+
+extern "C" rs_status rs_plan_set_tile(rs_plan *pl, const char *tile)
+{
+    if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
+    if (pl->form != RS_FORM_MFMA_SPLIT16) return rs_fail(RS_E_UNSUPPORTED, "tile configurations belong to matrix-core plans");
+    int wn, tl, nw, il;
+    if (!parse_tile(tile, &wn, &tl, &nw, &il))
+        return rs_fail(RS_E_INVALID, "tile \"%s\" is not a built configuration", tile ? tile : "(null)");
+    set_mfma_shape(pl, wn, tl, nw, il);
+    return RS_OK;
 }
 
 extern "C" rs_status rs_plan_tune(rs_plan *pl, const rs_pixels *px, void *cube, int32_t reps, void *stream,
@@ -482,8 +514,10 @@ extern "C" rs_status rs_plan_tune(rs_plan *pl, const rs_pixels *px, void *cube, 
     rs_status s = rs_check_pixels(pl, px);
     if (s != RS_OK) return s;
     if (pl->form == RS_FORM_MFMA_SPLIT16) {
-        static const int shapes[][3] = {{64, 128, 4}, {32, 128, 4}, {32, 128, 8}, {32, 64, 4},
-                                        {32, 64, 8},  {64, 64, 4},  {64, 64, 8},  {128, 64, 4}};
+        // every built shape; 8-wave shapes with both schedules
+        static const int shapes[][4] = {{64, 128, 4, 0}, {32, 128, 4, 0}, {32, 128, 8, 0}, {32, 128, 8, 1},
+                                        {32, 64, 4, 0},  {32, 64, 8, 0},  {32, 64, 8, 1},  {64, 64, 4, 0},
+                                        {64, 64, 8, 0},  {64, 64, 8, 1},  {128, 64, 4, 0}};
         device_guard g(pl->device);
         if (g.st != RS_OK) return g.st;
         hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -492,12 +526,12 @@ extern "C" rs_status rs_plan_tune(rs_plan *pl, const rs_pixels *px, void *cube, 
             if (e0) (void)hipEventDestroy(e0);
             return rs_fail(RS_E_DEVICE, "hipEventCreate failed");
         }
-        const int wn0 = pl->wn, tl0 = pl->tl, nw0 = pl->nw;
+        const int wn0 = pl->wn, tl0 = pl->tl, nw0 = pl->nw, il0 = pl->interleave;
         int best = -1;
         float best_ms = 0.f;
         for (int i = 0; i < (int)(sizeof shapes / sizeof shapes[0]) && s == RS_OK; ++i) {
             if (!rs_mfma_shape_supported(shapes[i][0], shapes[i][1], shapes[i][2])) continue;
-            set_mfma_shape(pl, shapes[i][0], shapes[i][1], shapes[i][2]);
+            set_mfma_shape(pl, shapes[i][0], shapes[i][1], shapes[i][2], shapes[i][3]);
             if ((s = rs_beat_synthesize(pl, px, cube, stream)) != RS_OK) break;
             (void)hipEventRecord(e0, st);
             for (int r = 0; r < reps && s == RS_OK; ++r) s = rs_beat_synthesize(pl, px, cube, stream);
@@ -513,16 +547,16 @@ extern "C" rs_status rs_plan_tune(rs_plan *pl, const rs_pixels *px, void *cube, 
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (s != RS_OK || best < 0) {
-            set_mfma_shape(pl, wn0, tl0, nw0);
+            set_mfma_shape(pl, wn0, tl0, nw0, il0);
             return s != RS_OK ? s : rs_fail(RS_E_UNSUPPORTED, "no tile shape could run");
         }
-        set_mfma_shape(pl, shapes[best][0], shapes[best][1], shapes[best][2]);
+        set_mfma_shape(pl, shapes[best][0], shapes[best][1], shapes[best][2], shapes[best][3]);
         // leave the cube computed with the chosen shape
         if ((s = rs_beat_synthesize(pl, px, cube, stream)) != RS_OK) return s;
         if (hipStreamSynchronize(st) != hipSuccess) return rs_fail(RS_E_DEVICE, "stream synchronisation failed");
     }
     if (chosen && chosen_len > 0) {
-        if (pl->form == RS_FORM_MFMA_SPLIT16) snprintf(chosen, chosen_len, "%dx%dx%d", pl->wn, pl->tl, pl->nw);
+        if (pl->form == RS_FORM_MFMA_SPLIT16) format_tile(pl, chosen, chosen_len);
         else chosen[0] = '\0';
     }
     return RS_OK;
@@ -544,17 +578,19 @@ extern "C" rs_status rs_plan_tune_cached(rs_plan *pl, const rs_pixels *px, void 
     long long pb = 1;
     while (pb < px->P) pb <<= 1;
     // the last well-formed entry with this key and a built shape wins
-    int hit_wn = 0, hit_tl = 0, hit_nw = 0;
+    int hit_wn = 0, hit_tl = 0, hit_nw = 0, hit_il = 0;
     if (std::FILE *f = std::fopen(cache_path, "r")) {
         char line[256];
         while (std::fgets(line, sizeof line, f)) {
-            int c = 0, ns = 0, l = 0, wn = 0, tl = 0, nw = 0;
+            int c = 0, ns = 0, l = 0, wn = 0, tl = 0, nw = 0, il = 0;
             long long b = 0;
-            if (std::sscanf(line, "%d %d %d %lld %dx%dx%d", &c, &ns, &l, &b, &wn, &tl, &nw) == 7 && c == pl->C &&
-                ns == pl->Ns && l == pl->L && b == pb && rs_mfma_shape_supported(wn, tl, nw)) {
+            char tile[64];
+            if (std::sscanf(line, "%d %d %d %lld %63s", &c, &ns, &l, &b, tile) == 5 && c == pl->C &&
+                ns == pl->Ns && l == pl->L && b == pb && parse_tile(tile, &wn, &tl, &nw, &il)) {
                 hit_wn = wn;
                 hit_tl = tl;
                 hit_nw = nw;
+                hit_il = il;
             }
         }
         const bool bad = std::ferror(f) != 0;
@@ -564,13 +600,14 @@ extern "C" rs_status rs_plan_tune_cached(rs_plan *pl, const rs_pixels *px, void 
         return rs_fail(RS_E_INVALID, "cannot open the tile cache %s", cache_path);
     }
     if (hit_wn) {
-        set_mfma_shape(pl, hit_wn, hit_tl, hit_nw);
-        if (chosen && chosen_len > 0) snprintf(chosen, chosen_len, "%dx%dx%d", pl->wn, pl->tl, pl->nw);
+        set_mfma_shape(pl, hit_wn, hit_tl, hit_nw, hit_il);
+        if (chosen && chosen_len > 0) format_tile(pl, chosen, chosen_len);
         return RS_OK;
     }
     if ((s = rs_plan_tune(pl, px, cube, reps, stream, chosen, chosen_len)) != RS_OK) return s;
-    char entry[128];
-    snprintf(entry, sizeof entry, "%d %d %d %lld %dx%dx%d\n", pl->C, pl->Ns, pl->L, pb, pl->wn, pl->tl, pl->nw);
+    char tile[32], entry[128];
+    format_tile(pl, tile, sizeof tile);
+    snprintf(entry, sizeof entry, "%d %d %d %lld %s\n", pl->C, pl->Ns, pl->L, pb, tile);
     std::FILE *f = std::fopen(cache_path, "a");
     const bool ok = f && std::fputs(entry, f) >= 0;
     if (f && std::fclose(f) != 0) return rs_fail(RS_E_INVALID, "cannot append to the tile cache %s", cache_path);

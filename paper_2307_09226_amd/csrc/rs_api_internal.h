@@ -19,6 +19,7 @@ struct rs_plan {
     // tile configuration
     int tn = 0, tl = 0, wn = 0;     // tile rows (n), tile columns (l), rows per wave (MFMA)
     int nw = 4;                     // waves per workgroup (MFMA)
+    int interleave = 0;             // MFMA, NW = 8: 1 = software-pipelined schedule, 0 = phase-shifted waves
     int n_tiles = 0, l_tiles = 0;
     int64_t items_target = 0;       // work items aimed at for one cube
     int min_chunk = 0;              // smallest pixel chunk

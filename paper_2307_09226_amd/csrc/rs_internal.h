@@ -87,7 +87,9 @@ __device__ __forceinline__ rs_item rs_decode_item(const rs_job &J, int64_t local
 // Kernel entry points (defined in the .hip files, launched by rs_api.hip).
 void rs_launch_plain(const rs_launch &L, int tl, int grid, hipStream_t st);
 // block_strength: some job of the launch has amp_lstride != 0
-void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, bool block_strength, int grid, hipStream_t st);
+// interleave: software-pipelined schedule also for NW = 8 (else phase-shifted waves)
+void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, bool interleave, bool block_strength, int grid,
+                    hipStream_t st);
 bool rs_mfma_shape_supported(int wn, int tl, int nw);
 void rs_launch_reduce(const rs_launch &L, int form, hipStream_t st);
 // block_strength: some job of the launch has strengths per block

@@ -56,8 +56,6 @@
 #include "rs_device.h"
 #include "rs_split16.h"
 
-#include <cstdlib>
-#include <mutex>
 #include <type_traits>
 
 namespace {
@@ -669,38 +667,30 @@ __global__ __launch_bounds__(256) void k_chunk_scale(rs_launch Lc)
     }
 }
 
-// Phase-shifted waves (RS_MFMA_PHASE=0 disables, for tuning).
-bool phase_enabled()
-{
-    static const bool on = [] {
-        const char *v = std::getenv("RS_MFMA_PHASE");
-        return !(v && v[0] == '0');
-    }();
-    return on;
-}
-
+// interleave: the software-pipelined schedule for NW = 8 too (shapes with
+// NW = 4 always use it)
 template <int WN, int TL, int NW, bool BS>
-void launch_one(const rs_launch &L, int grid, hipStream_t st)
+void launch_one(const rs_launch &L, bool interleave, int grid, hipStream_t st)
 {
-    if (NW == 8 && phase_enabled())
+    if (NW == 8 && !interleave)
         hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, true, BS>), dim3(grid), dim3(64 * NW), 0, st, L);
     else
         hipLaunchKernelGGL((k_mfma_split16<WN, TL, NW, false, BS>), dim3(grid), dim3(64 * NW), 0, st, L);
 }
 
 template <bool BS>
-void launch_shape(const rs_launch &L, int wn, int tl, int nw, int grid, hipStream_t st)
+void launch_shape(const rs_launch &L, int wn, int tl, int nw, bool interleave, int grid, hipStream_t st)
 {
     if (tl == 128) {
-        if (wn == 64) launch_one<64, 128, 4, BS>(L, grid, st);
-        else if (nw == 8) launch_one<32, 128, 8, BS>(L, grid, st);
-        else launch_one<32, 128, 4, BS>(L, grid, st);
+        if (wn == 64) launch_one<64, 128, 4, BS>(L, interleave, grid, st);
+        else if (nw == 8) launch_one<32, 128, 8, BS>(L, interleave, grid, st);
+        else launch_one<32, 128, 4, BS>(L, interleave, grid, st);
     } else {
-        if (wn == 32 && nw == 8) launch_one<32, 64, 8, BS>(L, grid, st);
-        else if (wn == 32) launch_one<32, 64, 4, BS>(L, grid, st);
-        else if (wn == 64 && nw == 8) launch_one<64, 64, 8, BS>(L, grid, st);
-        else if (wn == 64) launch_one<64, 64, 4, BS>(L, grid, st);
-        else launch_one<128, 64, 4, BS>(L, grid, st);
+        if (wn == 32 && nw == 8) launch_one<32, 64, 8, BS>(L, interleave, grid, st);
+        else if (wn == 32) launch_one<32, 64, 4, BS>(L, interleave, grid, st);
+        else if (wn == 64 && nw == 8) launch_one<64, 64, 8, BS>(L, interleave, grid, st);
+        else if (wn == 64) launch_one<64, 64, 4, BS>(L, interleave, grid, st);
+        else launch_one<128, 64, 4, BS>(L, interleave, grid, st);
     }
 }
 
@@ -714,12 +704,13 @@ bool rs_mfma_shape_supported(int wn, int tl, int nw)
                          (wn == 128 && nw == 4)));
 }
 
-void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, bool block_strength, int grid, hipStream_t st)
+void rs_launch_mfma(const rs_launch &L, int wn, int tl, int nw, bool interleave, bool block_strength, int grid,
+                    hipStream_t st)
 {
     if (block_strength)
-        launch_shape<true>(L, wn, tl, nw, grid, st);
+        launch_shape<true>(L, wn, tl, nw, interleave, grid, st);
     else
-        launch_shape<false>(L, wn, tl, nw, grid, st);
+        launch_shape<false>(L, wn, tl, nw, interleave, grid, st);
 }
 
 void rs_launch_chunk_scale(const rs_launch &L, bool block_strength, hipStream_t st)

@@ -240,7 +240,7 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
     const int nscale = nj - js;
     // main jobs grouped by tile shape
     struct group {
-        int wn, tl, nw, j0, n;
+        int wn, tl, nw, il, j0, n;
         int64_t items;
         const rs_plan *pl;
         bool block_strength;  // some request of the group has strengths per block
@@ -249,13 +249,19 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
     for (const auto &p : parts) {
         bool found = false;
         for (auto &g : groups)
-            if (g.wn == p.r->plan->wn && g.tl == p.r->plan->tl && g.nw == p.r->plan->nw) found = true;
-        if (!found) groups.push_back(group{p.r->plan->wn, p.r->plan->tl, p.r->plan->nw, 0, 0, 0, p.r->plan, false});
+            if (g.wn == p.r->plan->wn && g.tl == p.r->plan->tl && g.nw == p.r->plan->nw &&
+                g.il == p.r->plan->interleave)
+                found = true;
+        if (!found)
+            groups.push_back(group{p.r->plan->wn, p.r->plan->tl, p.r->plan->nw, p.r->plan->interleave, 0, 0, 0,
+                                   p.r->plan, false});
     }
     for (auto &g : groups) {
         g.j0 = nj;
         for (const auto &p : parts) {
-            if (p.r->plan->wn != g.wn || p.r->plan->tl != g.tl || p.r->plan->nw != g.nw) continue;
+            if (p.r->plan->wn != g.wn || p.r->plan->tl != g.tl || p.r->plan->nw != g.nw ||
+                p.r->plan->interleave != g.il)
+                continue;
             rs_job j = rs_make_job(p.r->plan, &p.r->px, p.r->cube, s->arena + p.r->arena_off,
                                    p.r->S, p.r->chunk);
             j.item_begin = g.items;

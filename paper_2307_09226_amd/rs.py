@@ -99,6 +99,7 @@ SIGNATURES = {
                                     ctypes.c_char_p, ctypes.c_size_t]),
     "rs_plan_tune_cached": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, ctypes.c_int32, _VP,
                                            ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]),
+    "rs_plan_set_tile": (ctypes.c_int, [_VP, ctypes.c_char_p]),
     "rs_beat_synthesize": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP]),
     "rs_beat_synthesize_ws": (ctypes.c_int, [_VP, ctypes.POINTER(rs_pixels), _VP, _VP,
                                              ctypes.c_size_t, _VP]),
@@ -281,6 +282,12 @@ def new_cube(plan: Plan, device="cuda:0", count: Optional[int] = None):
     import torch
     shape = plan.cube_shape if count is None else (count,) + plan.cube_shape
     return torch.empty(shape, dtype=plan.torch_dtype, device=device)
+
+
+def rs_plan_set_tile(plan: Plan, tile: str) -> None:
+    """Sets the matrix-core tile configuration ("WNxTLxNW", optional 'i'
+    suffix for the pipelined schedule of 8-wave shapes)."""
+    _check(lib.rs_plan_set_tile(plan.handle, tile.encode()))
 
 
 def rs_plan_tune(plan: Plan, pixels: DevicePixels, cube, reps: int = 3, stream=None) -> str:

@@ -12,7 +12,15 @@ from gpu_util import GATE_MFMA, errors, sample_indices
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {"64x128x4", "32x128x4", "32x128x8", "32x64x4", "32x64x8", "64x64x4", "64x64x8", "128x64x4"}
+SHAPES = {"64x128x4", "32x128x4", "32x128x8", "32x64x4", "32x64x8", "64x64x4", "64x64x8", "128x64x4",
+          # the 8-wave shapes with the software-pipelined schedule
+          "32x128x8i", "32x64x8i", "64x64x8i"}
+
+
+def _tile_of(desc):
+    """Configuration string of a plan description."""
+    pipe = desc["waves"] == 8 and desc["schedule"] == "pipelined"
+    return f"{desc['wave_rows']}x{desc['tile_l']}x{desc['waves']}" + ("i" if pipe else "")
 
 
 def test_tune_picks_a_built_shape_and_keeps_parity():
@@ -27,7 +35,7 @@ def test_tune_picks_a_built_shape_and_keeps_parity():
     print("tuned tile", chosen, flush=True)
     assert chosen in SHAPES
     desc = json.loads(plan.describe(px.P))
-    assert f"{desc['wave_rows']}x{desc['tile_l']}x{desc['waves']}" == chosen
+    assert _tile_of(desc) == chosen
     # the cube left by the tuning call and a fresh one both match the oracle
     c, l, n = sample_indices(radar.cube_shape(), 200, seed=5)
     ref = oracle.entries(radar, px, c, l, n)
@@ -78,7 +86,7 @@ def test_tune_cache_miss_then_hit(tmp_path):
     torch.cuda.synchronize()
     assert torch.all(cube2 == complex(3.0, -1.0))          # a hit launches nothing
     desc = json.loads(plan2.describe(px.P))
-    assert f"{desc['wave_rows']}x{desc['tile_l']}x{desc['waves']}" == shape
+    assert _tile_of(desc) == shape
     rs.rs_beat_synthesize(plan2, d, cube2)
     torch.cuda.synchronize()
     assert torch.equal(cube1, cube2)
@@ -94,10 +102,12 @@ def test_tune_cache_miss_then_hit(tmp_path):
 
 @pytest.mark.parametrize("model", [0, 16])
 def test_every_tile_shape_full_cube(tmp_path, model):
-    """Each tile shape the library builds, forced through the tile cache, on
-    a radar whose n and l axes leave ragged tiles for every shape: the full
-    cube matches the oracle and a second run gives the same bits (a missing
-    barrier or a wrong tail guard in one shape shows up here)."""
+    """Each tile configuration the library builds (both schedules of the
+    8-wave shapes), forced through the tile cache, on a radar whose n and l
+    axes leave ragged tiles for every shape: the full cube matches the
+    oracle, a second run gives the same bits, and the two schedules of an
+    8-wave shape give the same bits (a missing barrier or a wrong tail guard
+    in one shape shows up here)."""
     import dataclasses
     import torch
     from paper_2307_09226_amd import rs
@@ -107,6 +117,7 @@ def test_every_tile_shape_full_cube(tmp_path, model):
         px = scenes.block_strengths(px, radar.L, seed=6)
     ref = oracle.cube(radar, px)
     d = rs.DevicePixels.from_host(px)
+    first = {}
     for shape in sorted(SHAPES):
         path = str(tmp_path / f"tiles_{shape}.txt")
         with open(path, "w") as f:
@@ -123,4 +134,36 @@ def test_every_tile_shape_full_cube(tmp_path, model):
         print(f"tile {shape} model={model}: relL2 {rel:.2e} maxabs {mx:.2e}", flush=True)
         assert rel <= GATE_MFMA and mx <= GATE_MFMA, shape
         assert torch.equal(cube, again), shape
+        # the two schedules of one shape chunk the pixels alike: same bits
+        base = shape.rstrip("i")
+        if base in first:
+            assert torch.equal(cube, first[base]), shape
+        first[base] = cube
         plan.close()
+
+
+def test_set_tile_and_refusals():
+    """rs_plan_set_tile takes every built configuration (the plan describes
+    it) and refuses strings that are not one, leaving the plan unchanged;
+    plans of the other forms refuse it."""
+    import json
+    from paper_2307_09226_amd import rs
+    radar = scenes.radar_frame()
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=1000)
+    assert json.loads(plan.describe(1000))["schedule"] == "phase_shifted"   # the rule's 32x128x8
+    for t in sorted(SHAPES):
+        rs.rs_plan_set_tile(plan, t)
+        assert _tile_of(json.loads(plan.describe(1000))) == t
+    rs.rs_plan_set_tile(plan, "64x64x4i")                                    # accepted, no effect
+    assert _tile_of(json.loads(plan.describe(1000))) == "64x64x4"
+    for bad in ("48x128x8", "32x128x8x", "32x128", "", "32x128x8j", "64x128x8"):
+        with pytest.raises(rs.RSError) as e:
+            rs.rs_plan_set_tile(plan, bad)
+        assert e.value.status == rs.RS_E_INVALID
+    assert _tile_of(json.loads(plan.describe(1000))) == "64x64x4"
+    pplan = rs.rs_cube_plan(scenes.radar_small(), rs.RS_FORM_FP64_DIRECT, rs.RS_C64, max_pixels=10)
+    with pytest.raises(rs.RSError) as e:
+        rs.rs_plan_set_tile(pplan, "32x128x8")
+    assert e.value.status == rs.RS_E_UNSUPPORTED
+    plan.close()
+    pplan.close()
