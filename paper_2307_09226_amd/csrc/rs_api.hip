@@ -66,7 +66,9 @@ size_t rs_partial_bytes(const rs_plan *pl, int32_t S)
 
 size_t rs_workspace_bytes(const rs_plan *pl, int32_t S)
 {
-    size_t scale = pl->form == RS_FORM_MFMA_SPLIT16 ? (((size_t)S * 4 + 255) & ~(size_t)255) : 0;
+    size_t scale = pl->form == RS_FORM_MFMA_SPLIT16 && (pl->model & RS_MODEL_BLOCK_STRENGTH)
+                       ? (((size_t)S * 4 + 255) & ~(size_t)255)
+                       : 0;
     return rs_partial_bytes(pl, S) + scale;
 }
 
@@ -110,7 +112,9 @@ rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *par
     j.dtype = pl->dtype == RS_C128 ? 1 : 0;
     j.seg_begin = 0;
     j.seg_end = 0x7fffffff;
-    j.scale = pl->form == RS_FORM_MFMA_SPLIT16 && partial
+    // chunk scales come from k_chunk_scale only for strengths per block; the
+    // main kernel finds the others itself
+    j.scale = pl->form == RS_FORM_MFMA_SPLIT16 && partial && (pl->model & RS_MODEL_BLOCK_STRENGTH)
                   ? reinterpret_cast<int32_t *>(static_cast<char *>(partial) + rs_partial_bytes(pl, S))
                   : nullptr;
     return j;
@@ -640,7 +644,7 @@ extern "C" rs_status rs_beat_synthesize_ws(rs_plan *pl, const rs_pixels *px, voi
     std::memset(&L, 0, sizeof L);
     L.inline_job = rs_make_job(pl, px, cube, ws, S, chunk);
     L.njobs = 1;
-    if (pl->form == RS_FORM_MFMA_SPLIT16 && S > 0) {
+    if (pl->form == RS_FORM_MFMA_SPLIT16 && S > 0 && (pl->model & RS_MODEL_BLOCK_STRENGTH)) {
         rs_launch Sc = L;
         Sc.total = S;
         if ((s = rs_launch_scale_checked(Sc, (pl->model & RS_MODEL_BLOCK_STRENGTH) != 0, st)) != RS_OK) return s;
@@ -812,7 +816,7 @@ extern "C" rs_status rs_beat_synthesize_batch(rs_plan *pl, const rs_pixels *fram
     L.total = items;
     L.counter = reinterpret_cast<int *>(ws);
     s = RS_OK;
-    if (pl->form == RS_FORM_MFMA_SPLIT16 && chunks > 0) {
+    if (pl->form == RS_FORM_MFMA_SPLIT16 && chunks > 0 && (pl->model & RS_MODEL_BLOCK_STRENGTH)) {
         rs_launch Sc = L;
         Sc.counter = nullptr;
         Sc.total = chunks;

@@ -36,8 +36,9 @@
 // every rotation factor is itself reduced in binary64, so the error stays at
 // a few binary32 ulp (well below the fp16 hi/lo resolution of ~2^-22).
 //
-// Pixel strengths are scaled per chunk by an exact power of two (computed by
-// k_chunk_scale) so that the largest maps into [2^14, 2^15) and fp16 keeps
+// Pixel strengths are scaled per chunk by an exact power of two (found by
+// each work item from its chunk's strengths, or by k_chunk_scale for
+// strengths per block) so that the largest maps into [2^14, 2^15) and fp16 keeps
 // its relative precision for the small ones; the partial sum is scaled back
 // exactly when it is written.
 //
@@ -121,6 +122,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
     __shared__ pix_par sPar[2][kPB];
     __shared__ rs_item_consts sK;
     __shared__ int64_t sItem;
+    __shared__ float sRed[NW];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -145,8 +147,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         const bool seg_first = k0 == 0, seg_last = k1 == nsteps;
         const bool full_tile = n0 + TN <= J.Ns && l0 + TL <= J.L;
         const int m = it.c / J.N, r = it.c % J.N;
-        const int sh = J.scale[it.s];
-        const float a_scale = ldexpf(1.0f, sh);
+        // strength exponent shift of the chunk: from k_chunk_scale where the
+        // job has a scale array (strengths per block), else found below
+        int sh = J.scale ? J.scale[it.s] : 0;
+        float a_scale = 1.0f;
         const bool per_block = BS && J.amp_lstride != 0;
         // every reader of the previous item's sK has passed a barrier since
         if (tid == 0) rs_item_consts_of(J, m, r, sK);
@@ -535,9 +539,30 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             __syncthreads();
         };
 
+        // The chunk's exponent shift sh = 14 - floor(log2(max |a|)), as
+        // k_chunk_scale computes it, found by the item itself while the first
+        // parameter block is in flight (every item of the chunk finds the
+        // same value).
+        auto chunk_shift = [&]() {
+            float am = 0.f;
+            for (int64_t p = pb + tid; p < pe; p += NT) am = fmaxf(am, fabsf(rs_gload(sK.amp, p)));
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) am = fmaxf(am, __shfl_xor(am, o));
+            if (lane == 0) sRed[wave] = am;
+            __syncthreads();
+            am = sRed[0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) am = fmaxf(am, sRed[w]);
+            const int ex = (am > 0.f && am <= 3.4e38f) ? ilogbf(am) : kAmpExp;
+            const int v = kAmpExp - ex;
+            return v > 126 ? 126 : (v < -126 ? -126 : v);
+        };
+
         fops fa, fb;
         __syncthreads();  // previous item's readers of the LDS buffers are done
         fetch_block(k0 / kSPB);
+        if (!J.scale) sh = chunk_shift();
+        a_scale = ldexpf(1.0f, sh);
         load_block(k0 / kSPB);
         __syncthreads();
         gen_d(k0, buf0_t{});  // k0 is even: buffer 0
@@ -641,7 +666,9 @@ __global__ __launch_bounds__(256) void k_chunk_rowmax(rs_launch Lc)
 // Per-chunk strength scale: sh = 14 - floor(log2(max |a|)) so that the
 // largest scaled strength of the chunk (over all blocks when strengths vary
 // per block: the row-group maxima left by k_chunk_rowmax) lies in
-// [2^14, 2^15).
+// [2^14, 2^15).  Only jobs with strengths per block carry a scale array
+// (the L x P strengths are too many to scan inside each work item); the
+// main kernel finds the shift of the others itself.
 __global__ __launch_bounds__(256) void k_chunk_scale(rs_launch Lc)
 {
     __shared__ float red[4];
@@ -649,6 +676,7 @@ __global__ __launch_bounds__(256) void k_chunk_scale(rs_launch Lc)
     if (gch >= Lc.total) return;
     const int jidx = rs_find_job<RS_BY_CHUNK>(Lc, gch);
     const rs_job &J = rs_job_of(Lc, jidx);
+    if (!J.scale) return;  // the main kernel finds this job's shifts itself
     const int s = (int)(gch - J.chunk_begin);
     const int64_t pb = (int64_t)s * J.chunk;
     const int64_t pe = min(J.P, pb + (int64_t)J.chunk);

@@ -229,7 +229,9 @@ hipError_t enqueue_slice(rs_session *s, ring_slot &rg, const std::vector<slice_p
     int64_t chunks = 0;
     bool scale_bs = false;  // some new request has strengths per block
     for (const auto &p : parts) {
-        if (!p.scale) continue;
+        // chunk scales of requests with strengths per block (the main kernel
+        // finds the others itself)
+        if (!p.scale || !(p.r->plan->model & RS_MODEL_BLOCK_STRENGTH)) continue;
         rs_job j = rs_make_job(p.r->plan, &p.r->px, p.r->cube, s->arena + p.r->arena_off, p.r->S,
                                p.r->chunk);
         j.chunk_begin = chunks;

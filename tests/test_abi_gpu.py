@@ -97,9 +97,16 @@ def test_plan_describe_and_workspace():
     import json
     d = json.loads(plan.describe(px.P))
     assert d["form"] == "mfma_split16" and d["chunks"] >= 1
-    # partial sums of every chunk + one scale exponent per chunk (256-byte padded)
-    scale_bytes = (d["chunks"] * 4 + 255) // 256 * 256
-    assert plan.workspace_bytes(px.P) == d["chunks"] * 12 * 128 * 256 * 8 + scale_bytes
+    # partial sums of every chunk (the kernel finds the chunk scales itself)
+    assert plan.workspace_bytes(px.P) == d["chunks"] * 12 * 128 * 256 * 8
+    # with strengths per block, plus one scale exponent per chunk (256-byte padded)
+    import dataclasses
+    bplan = rs.rs_cube_plan(dataclasses.replace(radar, model=16), rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64,
+                            max_pixels=px.P)
+    db = json.loads(bplan.describe(px.P))
+    scale_bytes = (db["chunks"] * 4 + 255) // 256 * 256
+    assert bplan.workspace_bytes(px.P) == db["chunks"] * 12 * 128 * 256 * 8 + scale_bytes
+    bplan.close()
     # a pixel count whose chunks would exceed 2^30 pixels is refused, not wrapped
     big = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=1 << 40)
     with pytest.raises(rs.RSError) as e:
