@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rate", type=float, default=SERVING_RATE,
                     help="requests/s; 0 = 0.6 x the capacity measured in this run")
+    ap.add_argument("--serving-policy", choices=("shortest", "equal"), default="shortest")
+    ap.add_argument("--serving-slice-terms", type=float, default=0.0,
+                    help="terms per slice of the serving loop (0 = the library's default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (the "
@@ -497,10 +500,18 @@ def serving(rs, scenes, dev, args):
         items.append((plans[key], rs.DevicePixels.from_host(q.pixels, dev), q.terms))
     mean_terms = float(np.mean([t for _, _, t in items]))
     max_slots = 16
-    sess = rs.Session(hbm_budget=16 << 30, max_slots=max_slots, queue_cap=100000)
+    policy = {"shortest": rs.RS_SCHED_SHORTEST, "equal": rs.RS_SCHED_EQUAL}[args.serving_policy]
+    sess = rs.Session(hbm_budget=16 << 30, max_slots=max_slots, queue_cap=100000, policy=policy,
+                      slice_terms=args.serving_slice_terms)
     # one output buffer per pool entry; a request writes its entry's buffer
     bufs = [rs.new_cube(p, dev) for p, _, _ in items]
     torch.cuda.synchronize()
+    # each pool request alone (rs_beat_synthesize, median of 3 after a warm-up):
+    # the service time a request's latency is compared with (its slowdown)
+    alone_ms = []
+    for k, (p, d, _) in enumerate(items):
+        _, per = timed_steps(lambda: rs.rs_beat_synthesize(p, d, bufs[k]), 3, 1)
+        alone_ms.append(float(np.median(per)))
 
     def run(order, arrivals):
         tickets = []
@@ -538,15 +549,20 @@ def serving(rs, scenes, dev, args):
     lat = np.asarray(lat)
     sizes = np.array([items[k][2] for k in order])
     small = sizes <= np.median(sizes)
+    slow = lat / np.array([alone_ms[k] for k in order])
     return {"workload": "Poisson arrivals of mixed requests (1x4, 3x4, 12x16 arrays; Ns 128/256/512; "
                         "L 64/128/256; 4k-262k pixels), drawn from a pool of 48 seeded requests",
+            "policy": args.serving_policy, "slice_terms": args.serving_slice_terms or 1.2e11,
             "pool_mean_terms": mean_terms, "capacity_terms_per_s": cap_terms,
             "rate_req_per_s": rate, "offered_terms_per_s": rate * mean_terms, "requests": n,
             "throughput_req_per_s": n / wall, "terms_per_s": terms / wall,
-            "latency_p50_ms": pct(lat, 50), "latency_p99_ms": pct(lat, 99),
+            "latency_p50_ms": pct(lat, 50), "latency_p99_ms": pct(lat, 99), "latency_mean_ms": float(lat.mean()),
             "latency_p50_ms_small_half": pct(lat[small], 50), "latency_p99_ms_small_half": pct(lat[small], 99),
+            "slowdown_p50": pct(slow, 50), "slowdown_p99": pct(slow, 99),
+            "slowdown_note": "latency / the request's own rs_beat_synthesize time alone (median of 3)",
+            "alone_ms_p50": pct(alone_ms, 50), "alone_ms_max": float(np.max(alone_ms)),
             "launches": int(st["launches"]), "footprint_peak_bytes": int(st["footprint_peak"]),
-            "max_slots": max_slots}
+            "request_bytes_peak": int(st["request_bytes_peak"]), "max_slots": max_slots}
 
 
 if __name__ == "__main__":

@@ -276,7 +276,7 @@ rs_status rs_beat_synthesize_ws(rs_plan *plan, const rs_pixels *pixels, void *cu
 rs_status rs_beat_synthesize_noalloc(rs_plan *plan, const rs_pixels *pixels, void *cube,
                                      void *hip_stream);
 
-/* Enqueue `nframes` cubes that share one plan/* Enqueue `nframes` cubes that share one plan (e.g. consecutive animation
+/* Enqueue `nframes` cubes that share one plan (e.g. consecutive animation
  * frames with different pixel counts) as ONE persistent launch over all
  * frames' work items plus one reduction launch (NUFFT plans: the frames'
  * launches one after another on one workspace).  frames: HOST array of
@@ -292,20 +292,39 @@ void rs_plan_destroy(rs_plan *plan);
 
 /* ------------------------------------------------------------- sessions -- */
 /* A session is a serving loop with continuous batching: a scheduler thread
- * admits queued cube requests while the admitted HBM footprint stays within
- * hbm_budget and a slot is free, slices every admitted request into fixed
- * pixel-chunk work items, and runs persistent MFMA-form launches that mix
- * work items of all admitted requests.  A request that arrives while others
- * run is admitted as soon as memory and a slot free up.  A request's cube is
- * bitwise identical whatever else runs beside it. */
+ * admits queued cube requests while a slot is free and the request's split-K
+ * partial sums fit the session's HBM arena (hbm_budget), cuts the admitted
+ * requests' work into time slices of about slice_terms terms, and runs each
+ * slice as persistent MFMA-form launches that mix work items of all admitted
+ * requests.  A request that arrives while others run is admitted as soon as
+ * memory and a slot free up; requests that fit may overtake one that does
+ * not (at most 64 times, then it is admitted first), unless strict_fifo is
+ * set.  A request's cube is bitwise identical whatever else runs beside it.
+ *
+ * Shares of a slice (policy):
+ *   RS_SCHED_SHORTEST  slices as large as equal shares would make them,
+ *                      given to the requests with the least work left first
+ *                      (shortest remaining processing time) after a floor of
+ *                      1/8 of an equal share for every admitted request so
+ *                      that none stalls: small requests finish within a
+ *                      slice or two, large ones take the rest of each slice;
+ *   RS_SCHED_EQUAL     an equal share of slice_terms for each admitted
+ *                      request with work left (processor sharing); a slice
+ *                      is shorter when the requests need less than that. */
+
+typedef enum { RS_SCHED_SHORTEST = 0, RS_SCHED_EQUAL = 1 } rs_sched_policy;
 
 typedef struct {
     int32_t device;       /* HIP device ordinal                                  */
     size_t hbm_budget;    /* bytes of session workspace (partial sums) in flight */
     int32_t max_slots;    /* requests admitted at once (>= 1)                    */
     int32_t queue_cap;    /* requests queued before submit returns RS_E_BUSY     */
-    int32_t slice_items;  /* per request and launch: work items x 256-pixel steps;
-                             0 = automatic (~2 ms of matrix work per launch)      */
+    int32_t slice_items;  /* > 0: per request and slice about this many work
+                             items x 256-pixel steps (overrides slice_terms)      */
+    int32_t policy;       /* rs_sched_policy                                      */
+    int32_t strict_fifo;  /* 1: admit in arrival order only                       */
+    int32_t reserved;     /* 0 */
+    double slice_terms;   /* terms per slice; 0 = 1.2e11 (~2 ms of matrix work)  */
 } rs_session_opts;
 
 typedef enum {
@@ -317,15 +336,29 @@ typedef struct {
     int64_t t_submit_ns, t_admit_ns, t_done_ns; /* host CLOCK_MONOTONIC */
 } rs_timing;
 
+/* footprint_*: arena bytes held by admitted requests (what admission
+ * counts: the session allocates nothing else per request).  request_bytes_*:
+ * the HBM the admitted requests use in all -- their pixels (20 B per pixel,
+ * L x 4 + 16 B with strengths per block) and cubes, which the caller owns,
+ * plus the arena bytes.  device_error: 1 once a device error has stopped
+ * the session (text: rs_last_error after a failing submit). */
 typedef struct {
     int64_t submitted, admitted, done, failed, cancelled, launches;
     int64_t queued_now, running_now;
     size_t footprint_now, footprint_peak;
     double terms_done;
+    size_t request_bytes_now, request_bytes_peak;
+    int32_t device_error, reserved;
 } rs_session_stats;
 
 /* Start a session and its scheduler thread on opts->device.
- * Errors: RS_E_INVALID (bad options), RS_E_NOMEM, RS_E_DEVICE. */
+ * Errors: RS_E_INVALID (bad options: max_slots outside 1..4096, queue_cap
+ * < 1, slice_items < 0, unknown policy, slice_terms < 0 or not finite),
+ * RS_E_NOMEM, RS_E_DEVICE.
+ * After a device error (a failed launch reported by the device, or a failing
+ * completion query) the session stops: every admitted and queued request
+ * ends RS_REQ_FAILED, its arena range is freed, later submits return
+ * RS_E_DEVICE, and drain and destroy still return. */
 rs_status rs_session_create(const rs_session_opts *opts, rs_session **out);
 
 /* Queue one request: synthesize `pixels` with `plan` (which must use
@@ -357,6 +390,11 @@ void rs_session_destroy(rs_session *s);
  * without running, so their requests end FAILED (host-side; no kernel is
  * affected). */
 rs_status rs_session_inject_failure(rs_session *s, int32_t count);
+
+/* Test hook: the next completion check of this session reports a device
+ * error (host-side; the device is not touched), which stops the session as a
+ * real one would. */
+rs_status rs_session_inject_device_error(rs_session *s);
 
 /* ------------------------------------------------- scenes on the device -- */
 /* The paper obtains each frame's pixels (range, strength, angle, velocity)

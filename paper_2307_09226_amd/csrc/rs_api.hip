@@ -64,6 +64,8 @@ size_t rs_partial_bytes(const rs_plan *pl, int32_t S)
     return (b + 255) & ~(size_t)255;
 }
 
+size_t rs_scale_bytes(int32_t S) { return ((size_t)S * 4 + 255) & ~(size_t)255; }
+
 size_t rs_workspace_bytes(const rs_plan *pl, int32_t S)
 {
     size_t scale = pl->form == RS_FORM_MFMA_SPLIT16 && (pl->model & RS_MODEL_BLOCK_STRENGTH)

@@ -53,7 +53,8 @@ struct device_guard {
 void rs_choose_tiles(rs_plan *pl);
 rs_status rs_plan_chunking(const rs_plan *pl, int64_t P, int32_t *S, int32_t *chunk);
 size_t rs_partial_bytes(const rs_plan *pl, int32_t S);
-size_t rs_workspace_bytes(const rs_plan *pl, int32_t S);   // partials + chunk scales
+size_t rs_workspace_bytes(const rs_plan *pl, int32_t S);   // partials (+ chunk scales with strengths per block)
+size_t rs_scale_bytes(int32_t S);                            // a chunk-scale array
 int32_t rs_steps_per_chunk(const rs_plan *pl, int32_t chunk);
 rs_status rs_launch_scale_checked(const rs_launch &L, bool block_strength, hipStream_t st);
 rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *partial,

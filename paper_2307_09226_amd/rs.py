@@ -22,6 +22,7 @@ RS_FORM_FP64_DIRECT, RS_FORM_MFMA_SPLIT16, RS_FORM_NUFFT = 0, 1, 2
 RS_C64, RS_C128 = 0, 1
 RS_STATIC_SCRATCH_BYTES = 64 << 20  # include/rs.h: workspace of rs_beat_synthesize_noalloc
 RS_REQ_QUEUED, RS_REQ_RUNNING, RS_REQ_DONE, RS_REQ_FAILED, RS_REQ_CANCELLED = range(5)
+RS_SCHED_SHORTEST, RS_SCHED_EQUAL = 0, 1
 RS_MODEL_FAR_FIELD, RS_MODEL_TDM_SLOT, RS_MODEL_INTRA_CHIRP, RS_MODEL_RVP, RS_MODEL_BLOCK_STRENGTH = 1, 2, 4, 8, 16
 STATUS_NAMES = {0: "RS_OK", 1: "RS_E_INVALID", 2: "RS_E_NOMEM", 3: "RS_E_DEVICE",
                 4: "RS_E_UNSUPPORTED", 5: "RS_E_BUSY", 6: "RS_E_NOT_FOUND"}
@@ -50,7 +51,9 @@ class rs_pixels(ctypes.Structure):
 class rs_session_opts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t),
                 ("max_slots", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
-                ("slice_items", ctypes.c_int32)]
+                ("slice_items", ctypes.c_int32), ("policy", ctypes.c_int32),
+                ("strict_fifo", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("slice_terms", ctypes.c_double)]
 
 
 class rs_timing(ctypes.Structure):
@@ -64,7 +67,9 @@ class rs_session_stats(ctypes.Structure):
                 ("cancelled", ctypes.c_int64), ("launches", ctypes.c_int64),
                 ("queued_now", ctypes.c_int64), ("running_now", ctypes.c_int64),
                 ("footprint_now", ctypes.c_size_t), ("footprint_peak", ctypes.c_size_t),
-                ("terms_done", ctypes.c_double)]
+                ("terms_done", ctypes.c_double), ("request_bytes_now", ctypes.c_size_t),
+                ("request_bytes_peak", ctypes.c_size_t), ("device_error", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class rs_scene(ctypes.Structure):
@@ -117,6 +122,7 @@ SIGNATURES = {
     "rs_session_stats_get": (ctypes.c_int, [_VP, ctypes.POINTER(rs_session_stats)]),
     "rs_session_destroy": (None, [_VP]),
     "rs_session_inject_failure": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "rs_session_inject_device_error": (ctypes.c_int, [_VP]),
     "rs_range_doppler": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP]),
     "rs_render_scenes": (ctypes.c_int, [ctypes.POINTER(rs_scene), ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -416,8 +422,10 @@ class Session:
     """Owner of an rs_session handle (continuous-batching serving loop)."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_slots: int = 16,
-                 queue_cap: int = 4096, slice_items: int = 0):
-        opts = rs_session_opts(device, hbm_budget, max_slots, queue_cap, slice_items)
+                 queue_cap: int = 4096, slice_items: int = 0, policy: int = RS_SCHED_SHORTEST,
+                 strict_fifo: bool = False, slice_terms: float = 0.0):
+        opts = rs_session_opts(device, hbm_budget, max_slots, queue_cap, slice_items, policy,
+                               1 if strict_fifo else 0, 0, float(slice_terms))
         h = ctypes.c_void_p()
         _check(lib.rs_session_create(ctypes.byref(opts), ctypes.byref(h)))
         self.handle = h.value
@@ -461,6 +469,9 @@ class Session:
 
     def inject_failure(self, count: int = 1):
         _check(lib.rs_session_inject_failure(self.handle, count))
+
+    def inject_device_error(self):
+        _check(lib.rs_session_inject_device_error(self.handle))
 
     def close(self):
         if self.handle:

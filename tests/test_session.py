@@ -163,3 +163,65 @@ def test_plain_plan_rejected_and_zero_pixel_request():
     assert _wait(sess, [t])[t] == rs.RS_REQ_DONE
     assert torch.count_nonzero(cube).item() == 0
     sess.close()
+
+
+def test_both_policies_give_the_alone_cubes():
+    """Shortest-remaining-first and equal shares, in arrival order or with
+    overtaking, give every request the cube it has alone, bit for bit; the
+    stats count the requests' whole HBM (pixels, cubes, partial sums)."""
+    import torch
+    rs = _rs()
+    reqs = _requests(6)
+    plans = [rs.rs_cube_plan(q.radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=q.pixels.P)
+             for q in reqs]
+    dpx = [rs.DevicePixels.from_host(q.pixels) for q in reqs]
+    alone = []
+    for p, d in zip(plans, dpx):
+        c = rs.new_cube(p)
+        rs.rs_beat_synthesize(p, d, c)
+        alone.append(c)
+    torch.cuda.synchronize()
+    for policy, strict in ((rs.RS_SCHED_SHORTEST, False), (rs.RS_SCHED_EQUAL, True)):
+        sess = rs.Session(hbm_budget=2 << 30, max_slots=4, policy=policy, strict_fifo=strict,
+                          slice_terms=2e10)
+        cubes = [rs.new_cube(p) for p in plans]
+        tickets = [sess.submit(p, d, c) for p, d, c in zip(plans, dpx, cubes)]
+        states = _wait(sess, tickets)
+        assert all(s == rs.RS_REQ_DONE for s in states.values()), (policy, states)
+        for i, (a, b) in enumerate(zip(alone, cubes)):
+            assert torch.equal(a, b), (policy, i)
+        st = sess.stats()
+        assert st["request_bytes_peak"] > st["footprint_peak"] > 0
+        assert st["request_bytes_now"] == 0 and st["footprint_now"] == 0 and st["device_error"] == 0
+        sess.close()
+    with pytest.raises(rs.RSError) as e:
+        rs.Session(policy=7)
+    assert e.value.status == rs.RS_E_INVALID
+
+
+def test_device_error_stops_the_session():
+    """A device error seen at a completion check (injected from the host;
+    the device is untouched): every admitted and queued request ends FAILED,
+    later submits are refused with RS_E_DEVICE, and drain and close return."""
+    rs = _rs()
+    reqs = _requests(5, p_max=60000)
+    plans = [rs.rs_cube_plan(q.radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=q.pixels.P)
+             for q in reqs]
+    dpx = [rs.DevicePixels.from_host(q.pixels) for q in reqs]
+    sess = rs.Session(hbm_budget=4 << 30, max_slots=1, slice_terms=2e9)
+    cubes = [rs.new_cube(p) for p in plans]
+    tickets = [sess.submit(p, d, c) for p, d, c in zip(plans, dpx, cubes)]
+    sess.inject_device_error()
+    states = _wait(sess, tickets)
+    sess.drain()
+    st = sess.stats()
+    print("states after the device error:", states, st, flush=True)
+    assert st["device_error"] == 1
+    assert any(s == rs.RS_REQ_FAILED for s in states.values())
+    assert all(s in (rs.RS_REQ_DONE, rs.RS_REQ_FAILED) for s in states.values())
+    assert st["done"] + st["failed"] == len(reqs)
+    assert st["running_now"] == 0 and st["queued_now"] == 0 and st["footprint_now"] == 0
+    with pytest.raises(rs.RSError) as e:
+        sess.submit(plans[0], dpx[0], cubes[0])
+    assert e.value.status == rs.RS_E_DEVICE and "device error" in str(e.value)
+    sess.close()
