@@ -6,17 +6,37 @@
 //   X_c[k][d] = sum_l sum_n Y[c][l][n] exp(-j2pi k n / Ns) exp(+j2pi d l / L)
 //   power[k][d] = sum_c |X_c[k][d]|^2
 //
-// Three launches on the caller's stream:
+// Fused path (Ns = 256, L = 16 D2 with D2 in {1, 2, 4, 8}): one workgroup
+// holds a whole channel's L x 256 tile in registers, 64 entries a thread
+// (4 rows of 16), and takes it through both FFTs without touching HBM in
+// between:
+//   k_rd_fused   per workgroup (at most one per compute unit) a contiguous
+//                run of the (frame, channel) items; for each: fast-time
+//                FFT as 16 x 16 (16-point DFTs in registers, a transpose
+//                inside each wavefront through LDS), the tile's half
+//                spectra moved through LDS into the slow-time layout, the
+//                L-point inverse-sign FFT as 16 x D2 (the second factor
+//                read back from LDS written in place), |.|^2 accumulated in
+//                registers over the run's channels; one partial map per
+//                (workgroup, frame) written at the run's frame boundaries
+//   k_rd_merge   per (frame, block of 1024 cells): the partial maps of the
+//                workgroups that cover the frame summed in workgroup order
+//                -> power, and the block's maximum
+//   k_rd_peak    per frame: the maximum over the blocks, its range and
+//                velocity, and the velocity spectrum at its range bin
+// HBM traffic: the cubes read once, plus one partial map per (workgroup,
+// frame) written and read back, plus the map.
+//
+// Two-pass path (other shapes):
 //   k_range_fft      fast-time FFT of every (frame, channel, block) row in
 //                    LDS -> rf[F][C][L][Ns] (float2 workspace)
 //   k_doppler_power  per (frame, group of KB range bins): for each channel
 //                    the inverse-sign FFT over blocks in LDS, |.|^2 summed in
 //                    registers -> power[F][Ns][L]; plus the group's maximum
-//   k_rd_peak        per frame: the maximum over the groups, its range and
-//                    velocity, and the velocity spectrum at its range bin
-// The FFTs are iterative radix-2 (decimation in time, bit-reversed load) in
-// float32 with twiddles evaluated in binary64.  Memory bound: every cube
-// entry is read once and the float2 intermediate written and read once.
+//   k_rd_peak        as above
+// The LDS FFTs are iterative radix-2 (decimation in time, bit-reversed
+// load).  Both paths compute in float32 with twiddles evaluated in binary64;
+// both are deterministic (fixed operation and summation order).
 #include "rs_api_internal.h"
 #include "rs_fft.h"
 
@@ -139,6 +159,333 @@ __global__ __launch_bounds__(kThreads) void k_doppler_power(const float2 *rf, fl
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused path
+// ---------------------------------------------------------------------------
+constexpr int kFNs = 256;                 // fast-time length of the fused path
+constexpr int kFR = 16;                   // 256 = 16 x 16
+constexpr int kFHalf = kFNs / 2;          // range bins per slow-time half
+constexpr int kFX1 = kFR * (kFR + 1);     // one row of the fast-time transpose (padded, = 16 mod 32)
+constexpr int kMergeCells = 1024;         // cells per k_rd_merge workgroup
+constexpr int kFusedRows = 4;             // tile rows a thread holds (64 entries)
+
+// cos(2 pi m / 16), m taken modulo 16
+__host__ __device__ constexpr float cos16(int m)
+{
+    switch (m & 15) {
+    case 0: return 1.0f;
+    case 1: case 15: return 0.923879532511286756f;
+    case 2: case 14: return 0.707106781186547524f;
+    case 3: case 13: return 0.382683432365089772f;
+    case 4: case 12: return 0.0f;
+    case 5: case 11: return -0.382683432365089772f;
+    case 6: case 10: return -0.707106781186547524f;
+    case 7: case 9: return -0.923879532511286756f;
+    default: return -1.0f;
+    }
+}
+__host__ __device__ constexpr float sin16(int m) { return cos16(m + 12); }   // sin x = cos(x - pi/2)
+
+__host__ __device__ constexpr int brev_c(int v, int bits)
+{
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+
+// x * exp(SIGN j 2 pi m / 16) with the multiplications by 1 and +-j left out
+template <int SIGN>
+__device__ __forceinline__ float2 rot16(float2 x, int m)
+{
+    if (m == 0) return x;
+    if (m == 4) return make_float2(-(float)SIGN * x.y, (float)SIGN * x.x);
+    return cmul(x, make_float2(cos16(m), (float)SIGN * sin16(m)));
+}
+
+// In-register DFT of N <= 16 points, natural order in and out:
+// v[k] <- sum_n v[n] exp(SIGN j 2 pi n k / N); radix-2 decimation in time,
+// the bit reversal a renaming of registers.
+template <int N, int SIGN>
+__device__ __forceinline__ void dft_reg(float2 *v)
+{
+    constexpr int LOG = N >= 16 ? 4 : N >= 8 ? 3 : N >= 4 ? 2 : N >= 2 ? 1 : 0;
+    static_assert((1 << LOG) == N && N <= 16, "N must be a power of two <= 16");
+    float2 a[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] = v[brev_c(i, LOG)];
+#pragma unroll
+    for (int s = 0; s < LOG; ++s) {
+        const int half = 1 << s;
+#pragma unroll
+        for (int b = 0; b < N / 2; ++b) {
+            const int pos = b & (half - 1);
+            const int i = ((b >> s) << (s + 1)) + pos;
+            const float2 t = rot16<SIGN>(a[i + half], pos * (8 / half));
+            const float2 u = a[i];
+            a[i] = make_float2(u.x + t.x, u.y + t.y);
+            a[i + half] = make_float2(u.x - t.x, u.y - t.y);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = a[i];
+}
+
+// LDS ordering among the lanes of one wavefront: the wavefront's LDS
+// operations complete in issue order, so a fence that keeps the compiler
+// from moving them across suffices.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int D2, int RPT>
+struct rd_fused_shape {
+    static constexpr int L = 16 * D2;
+    static constexpr int T = 16 * L / RPT;          // threads: RPT rows of 16 tile entries each
+    static constexpr int IPT = RPT / 2;             // slow-time problems per thread and half
+    static constexpr int P = L + D2;                // padded row of the slow-time exchange
+    static constexpr int NW = T / 64;
+    static constexpr int X1 = NW * 4 * kFX1;        // fast-time transposes, 4 rows per wavefront
+    static constexpr int XB = kFHalf * P > X1 ? kFHalf * P : X1;
+    static constexpr size_t lds = (size_t)(XB + kFR * kFR + L) * sizeof(float2);
+    static_assert(T % 64 == 0 && RPT % 2 == 0, "whole wavefronts, rows in pairs");
+};
+
+// Workgroup w takes items [w n / W, (w + 1) n / W) of the n = F C items
+// (item = frame * C + channel, the cube order) and writes the power summed
+// over each frame's items in its run to slots[w J + frame - first frame].
+// Thread layouts (t = thread, T threads, RPT rows a thread):
+//   fast time   rows g + s L / RPT (g = t / 16, s < RPT); pass 1 holds
+//               n = q + 16 n1 (q = t % 16) and transforms over n1, pass 2
+//               holds k = q + 16 k2 and transforms over the other factor
+//   slow time   problems p = t + T i (i < RPT / 2) of half h: range bin
+//               128 h + p / D2; pass 1 holds l = j + D2 l1 (j = p % D2) and
+//               transforms over l1, pass 2 holds d1 = (16 / D2) j + e
+//               (e < 16 / D2) and transforms over the D2 values of j;
+//               cells (k, d = d1 + 16 d2)
+template <int D2, int RPT, typename IT>
+__global__ __launch_bounds__((rd_fused_shape<D2, RPT>::T)) void k_rd_fused(const IT *__restrict__ cubes,
+                                                                        float *__restrict__ slots, int C,
+                                                                        int64_t nitems, int W, int J)
+{
+    using S = rd_fused_shape<D2, RPT>;
+    constexpr int L = S::L, P = S::P, T = S::T, IPT = S::IPT;
+    constexpr int DI = 16 / D2;   // slow-time pass-2 problems per slow-time pass-1 problem
+    constexpr int LD2 = D2 >= 8 ? 3 : D2 >= 4 ? 2 : D2 >= 2 ? 1 : 0;
+    // LDS layouts (64 banks of 4 bytes: 32 float2 slots, 32 lanes served
+    // together by a 64-bit access), all free of bank conflicts:
+    //   slow-time exchange  entry (k, l) of a half at k P + (l ^ swz(k)),
+    //                       swz(k) < D2 spreading the rows that the
+    //                       16-lane groups of the write share a bank with
+    //   pass 1 -> pass 2    row k rewritten in place: pass-1 problem j's
+    //                       output d1 at D2 d1 + d1 / DI + j (one pad slot
+    //                       after each 16)
+    //   fast-time transpose rows of kFX1 = 16 (mod 32) slots
+    auto swz = [](int k) { return (((k * D2) >> 5) << 1) & (D2 - 1); };
+    extern __shared__ float2 smem[];
+    float2 *buf = smem;
+    // twiddles laid out so that a thread's own sit at fixed offsets from
+    // one base: twr[k1][q] = exp(-j 2 pi q k1 / 256), twd[d1][j] =
+    // exp(+j 2 pi j d1 / L)
+    float2 *twr = smem + S::XB;
+    float2 *twd = twr + kFR * kFR;
+    const int t = threadIdx.x;
+    const int g = t >> 4, q = t & 15, wv = t >> 6;
+    const int jj = t % D2;
+    const int sig = swz(q);   // = swz(q + 16 k2) for every k2
+    for (int m = t; m < kFR * kFR; m += T) {
+        double sn, cs;
+        sincospi(2.0 * (double)((m >> 4) * (m & 15)) / (double)kFNs, &sn, &cs);
+        twr[m] = make_float2((float)cs, (float)-sn);
+    }
+    for (int m = t; m < 16 * D2; m += T) {
+        double sn, cs;
+        sincospi(2.0 * (double)((m / D2) * (m % D2)) / (double)L, &sn, &cs);
+        twd[m] = make_float2((float)cs, (float)sn);
+    }
+    const int64_t i0 = (int64_t)blockIdx.x * nitems / W, i1 = ((int64_t)blockIdx.x + 1) * nitems / W;
+    const int64_t f0 = i0 / C;
+    float acc[2][IPT][DI][D2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < IPT; ++i)
+#pragma unroll
+            for (int e = 0; e < DI; ++e)
+#pragma unroll
+                for (int d = 0; d < D2; ++d) acc[h][i][e][d] = 0.f;
+
+    // the first PF rows of each next item are loaded under the current
+    // item's last slow-time pass (registers for more are not free)
+    constexpr int PF = 1;
+    float2 pre[PF][kFR];
+    const IT *tile = cubes + g * kFNs + q;
+#pragma unroll
+    for (int r = 0; r < PF; ++r)
+#pragma unroll
+        for (int n1 = 0; n1 < kFR; ++n1) pre[r][n1] = load_c(tile + min(i0, i1 - 1) * (int64_t)(L * kFNs) + r * (L / RPT) * kFNs + kFR * n1);
+    for (int64_t it = i0; it < i1; ++it) {
+        const IT *src = tile + it * (int64_t)(L * kFNs);
+        float2 v[RPT][kFR];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+#pragma unroll
+            for (int n1 = 0; n1 < kFR; ++n1)
+                v[r][n1] = r < PF ? pre[r][n1] : load_c(src + r * (L / RPT) * kFNs + kFR * n1);
+        __syncthreads();   // the previous item's slow-time reads of buf are done (and the tables written)
+        // fast time, one row at a time: 16-point DFT over n1, the product
+        // with exp(-j 2 pi q k1 / 256) stored transposed, 16-point DFT over
+        // the other factor -> v[r][k2] = X[row][q + 16 k2]
+        float2 *x1 = buf + (wv * 4 + (g & 3)) * kFX1;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            dft_reg<kFR, -1>(v[r]);
+            x1[q] = v[r][0];
+#pragma unroll
+            for (int k1 = 1; k1 < kFR; ++k1) x1[k1 * (kFR + 1) + q] = cmul(v[r][k1], twr[k1 * kFR + q]);
+            wave_sync();
+#pragma unroll
+            for (int n2 = 0; n2 < kFR; ++n2) v[r][n2] = x1[q * (kFR + 1) + n2];
+            wave_sync();
+            dft_reg<kFR, -1>(v[r]);
+            // finished spectra stay in registers: otherwise the compiler
+            // defers the last butterflies of the second half past the
+            // barriers below and holds both of their operands meanwhile
+#pragma unroll
+            for (int k = 0; k < kFR; ++k) asm volatile("" : "+v"(v[r][k].x), "+v"(v[r][k].y));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();   // transposes / the other half's reads are done
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+#pragma unroll
+                for (int k2 = 0; k2 < kFR / 2; ++k2)
+                    buf[(q + kFR * k2) * P + (g ^ sig) + r * (L / RPT)] = v[r][h * (kFR / 2) + k2];
+            if (h == 1) {
+                const IT *nsrc = tile + min(it + 1, i1 - 1) * (int64_t)(L * kFNs);
+#pragma unroll
+                for (int r = 0; r < PF; ++r)
+#pragma unroll
+                    for (int n1 = 0; n1 < kFR; ++n1) pre[r][n1] = load_c(nsrc + r * (L / RPT) * kFNs + kFR * n1);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int kl = (t + T * i) / D2;
+                // slow time, pass 1: 16-point DFT over l1, the product with
+                // exp(+j 2 pi j d1 / L) written back in place
+                float2 *row = buf + kl * P;
+                const float2 *col = row + (jj ^ swz(kl));
+                float2 u[16];
+#pragma unroll
+                for (int l1 = 0; l1 < 16; ++l1) u[l1] = col[D2 * l1];
+                dft_reg<16, +1>(u);
+                row += jj;
+                row[0] = u[0];
+#pragma unroll
+                for (int d1 = 1; d1 < 16; ++d1) row[D2 * d1 + (d1 >> (4 - LD2))] = cmul(u[d1], twd[d1 * D2 + jj]);
+            }
+            wave_sync();   // the D2 threads of a range bin are lanes of one wavefront
+#pragma unroll
+            for (int i = 0; i < IPT; ++i) {
+                const int kl = (t + T * i) / D2;
+                // slow time, pass 2: D2-point DFT over j for d1 = DI jj + e
+#pragma unroll
+                for (int e = 0; e < DI; ++e) {
+                    const float2 *z0 = buf + kl * P + 17 * jj + D2 * e;
+                    float2 z[D2];
+#pragma unroll
+                    for (int j = 0; j < D2; ++j) z[j] = z0[j];
+                    dft_reg<D2, +1>(z);
+#pragma unroll
+                    for (int d = 0; d < D2; ++d)
+                        acc[h][i][e][d] =
+                            __builtin_fmaf(z[d].x, z[d].x, __builtin_fmaf(z[d].y, z[d].y, acc[h][i][e][d]));
+                }
+            }
+        }
+        const int64_t f = it / C;
+        if (it + 1 == i1 || (it + 1) / C != f) {
+            float *dst = slots + ((int64_t)blockIdx.x * J + (f - f0)) * (int64_t)(kFNs * L);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < IPT; ++i) {
+                    const int kl = (t + T * i) / D2;
+#pragma unroll
+                    for (int e = 0; e < DI; ++e)
+#pragma unroll
+                        for (int d = 0; d < D2; ++d) {
+                            dst[(kFHalf * h + kl) * L + DI * jj + e + 16 * d] = acc[h][i][e][d];
+                            acc[h][i][e][d] = 0.f;
+                        }
+                }
+        }
+    }
+}
+
+// Per (frame, block of 1024 cells): the frame's partial maps summed in
+// workgroup order -> power, and the block's maximum (smallest cell index on
+// ties; d = 0 skipped when skip_static).
+__global__ __launch_bounds__(256) void k_rd_merge(const float *__restrict__ slots, float *__restrict__ power,
+                                                 rd_peak_part *parts, int C, int64_t nitems, int W, int J,
+                                                 int cells, int L, int skip_static)
+{
+    const int nblk = cells / kMergeCells;
+    const int64_t f = blockIdx.x / nblk;
+    const int b = blockIdx.x % nblk;
+    const int e = b * kMergeCells + threadIdx.x * 4;
+    const int64_t wlo = ((f * C + 1) * W - 1) / nitems, whi = ((f * C + C) * W - 1) / nitems;
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t w = wlo; w <= whi; ++w) {
+        const int64_t first = (w * nitems / W) / C;
+        const float4 p = *reinterpret_cast<const float4 *>(slots + (w * J + (f - first)) * (int64_t)cells + e);
+        s.x += p.x;
+        s.y += p.y;
+        s.z += p.z;
+        s.w += p.w;
+    }
+    *reinterpret_cast<float4 *>(power + f * (int64_t)cells + e) = s;
+    const float vals[4] = {s.x, s.y, s.z, s.w};
+    float best = -1.f;
+    int bidx = -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = e + i;
+        if (!(skip_static && (c & (L - 1)) == 0) && vals[i] > best) {
+            best = vals[i];
+            bidx = c;
+        }
+    }
+    __shared__ float rv[256];
+    __shared__ int ri[256];
+    rv[threadIdx.x] = best;
+    ri[threadIdx.x] = bidx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const float v2 = rv[threadIdx.x + o];
+            const int i2 = ri[threadIdx.x + o];
+            if (i2 >= 0 && (ri[threadIdx.x] < 0 || v2 > rv[threadIdx.x] ||
+                            (v2 == rv[threadIdx.x] && i2 < ri[threadIdx.x]))) {
+                rv[threadIdx.x] = v2;
+                ri[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        rd_peak_part p;
+        p.v = rv[0];
+        p.idx = ri[0];
+        parts[blockIdx.x] = p;
+    }
+}
+
 // Per frame: maximum over the groups (smallest index on ties), the peak
 // record and the velocity spectrum at the peak's range bin.
 __global__ __launch_bounds__(kThreads) void k_rd_peak(const rd_peak_part *parts, const float *power, int groups,
@@ -200,6 +547,43 @@ int ilog2_exact(int v)
     return l;
 }
 
+// Workgroups of the fused path: at most one per compute unit (a
+// workgroup's LDS fills one), as few as keep the longest run at
+// ceil(F C / compute units) items, the items split evenly over them; a
+// frame's items can fall into several runs, whose partial maps k_rd_merge
+// adds (fewer workgroups, fewer partial maps).
+int64_t rd_fused_workgroups(int64_t nframes, int C, int ncu)
+{
+    const int64_t n = nframes * C;
+    const int64_t per = (n + ncu - 1) / std::max(1, ncu);
+    return std::max<int64_t>(1, (n + per - 1) / per);
+}
+
+template <int D2, typename IT>
+hipError_t launch_fused(const void *cubes, float *slots, int C, int64_t nitems, int W, int J, hipStream_t st)
+{
+    constexpr int RPT = kFusedRows;
+    using S = rd_fused_shape<D2, RPT>;
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rd_fused<D2, RPT, IT>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_rd_fused<D2, RPT, IT>), dim3((unsigned)W), dim3(S::T), S::lds, st,
+                       reinterpret_cast<const IT *>(cubes), slots, C, nitems, W, J);
+    return hipGetLastError();
+}
+
+template <typename IT>
+hipError_t launch_fused_l(int L, const void *cubes, float *slots, int C, int64_t nitems, int W, int J,
+                          hipStream_t st)
+{
+    switch (L) {
+    case 16: return launch_fused<1, IT>(cubes, slots, C, nitems, W, J, st);
+    case 32: return launch_fused<2, IT>(cubes, slots, C, nitems, W, J, st);
+    case 64: return launch_fused<4, IT>(cubes, slots, C, nitems, W, J, st);
+    default: return launch_fused<8, IT>(cubes, slots, C, nitems, W, J, st);
+    }
+}
+
 }  // namespace
 
 extern "C" rs_status rs_range_doppler(rs_plan *pl, const void *cubes, int32_t nframes, int32_t skip_static,
@@ -218,48 +602,85 @@ extern "C" rs_status rs_range_doppler(rs_plan *pl, const void *cubes, int32_t nf
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
     const int Ns = pl->Ns, L = pl->L, C = pl->C;
-    const int64_t rows = (int64_t)nframes * C * L;
-    const int rpw = std::max(1, 2048 / Ns);
-    int kb = std::min(16, kGroupElems / L);
-    kb = std::min(kb, Ns);
-    const int groups = Ns / kb;
-    const size_t rf_bytes = (size_t)rows * Ns * sizeof(float2);
-    const size_t pw_bytes = power ? 0 : (size_t)nframes * Ns * L * sizeof(float);
-    const size_t part_bytes = (size_t)nframes * groups * sizeof(rd_peak_part);
+    const int64_t cells = (int64_t)Ns * L;
+    const bool fused = Ns == kFNs && L >= 16 && L <= 128;
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t total = up(rf_bytes) + up(pw_bytes) + up(part_bytes);
-    char *ws = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
-        return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", total);
-    float2 *rf = reinterpret_cast<float2 *>(ws);
-    float *pw = power ? power : reinterpret_cast<float *>(ws + up(rf_bytes));
-    rd_peak_part *parts = reinterpret_cast<rd_peak_part *>(ws + up(rf_bytes) + up(pw_bytes));
+    const float rpb = pl->mu != 0.0 ? (float)(pl->c0 * pl->Fs / (2.0 * pl->mu * Ns)) : 0.f;
+    const float vpb = pl->fc != 0.0 ? (float)(pl->c0 / (2.0 * pl->fc * pl->Tb * L)) : 0.f;
+    const size_t pw_bytes = power ? 0 : (size_t)(nframes * cells) * sizeof(float);
 
     rs_status s = RS_OK;
-    const int64_t g1 = (rows + rpw - 1) / rpw;
-    const size_t lds1 = (size_t)(Ns / 2 + rpw * Ns) * sizeof(float2);
-    if (pl->dtype == RS_C128)
-        hipLaunchKernelGGL(k_range_fft<double2>, dim3((unsigned)g1), dim3(kThreads), lds1, st,
-                           reinterpret_cast<const double2 *>(cubes), rf, rows, logn, rpw);
-    else
-        hipLaunchKernelGGL(k_range_fft<float2>, dim3((unsigned)g1), dim3(kThreads), lds1, st,
-                           reinterpret_cast<const float2 *>(cubes), rf, rows, logn, rpw);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "range FFT launch: %s", hipGetErrorString(e));
-    if (s == RS_OK) {
-        const size_t lds2 = (size_t)(L / 2 + kb * L) * sizeof(float2);
-        hipLaunchKernelGGL(k_doppler_power, dim3((unsigned)(nframes * groups)), dim3(kThreads), lds2, st, rf, pw,
-                           parts, C, logl, Ns, kb, skip_static ? 1 : 0);
+    hipError_t e;
+    char *ws = nullptr;
+    if (fused) {
+        // workspace: the partial maps [W][J][cells], the map when not
+        // wanted, the block maxima
+        const int64_t nitems = (int64_t)nframes * C;
+        const int64_t W = rd_fused_workgroups(nframes, C, pl->ncu);
+        const int64_t per = (nitems + W - 1) / W;
+        const int64_t J = (per - 1 + C - 1) / C + 1;   // frames a run of `per` items can touch
+        const int groups = (int)(cells / kMergeCells);
+        const size_t slot_bytes = (size_t)(W * J * cells) * sizeof(float);
+        const size_t part_bytes = (size_t)nframes * groups * sizeof(rd_peak_part);
+        const size_t total = up(slot_bytes) + up(pw_bytes) + up(part_bytes);
+        if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
+            return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", total);
+        float *slots = reinterpret_cast<float *>(ws);
+        float *pw = power ? power : reinterpret_cast<float *>(ws + up(slot_bytes));
+        rd_peak_part *parts = reinterpret_cast<rd_peak_part *>(ws + up(slot_bytes) + up(pw_bytes));
+        e = pl->dtype == RS_C128 ? launch_fused_l<double2>(L, cubes, slots, C, nitems, (int)W, (int)J, st)
+                                 : launch_fused_l<float2>(L, cubes, slots, C, nitems, (int)W, (int)J, st);
+        if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "fused range-Doppler launch: %s", hipGetErrorString(e));
+        if (s == RS_OK) {
+            hipLaunchKernelGGL(k_rd_merge, dim3((unsigned)(nframes * groups)), dim3(kMergeCells / 4), 0, st, slots,
+                               pw, parts, C, nitems, (int)W, (int)J, (int)cells, L, skip_static ? 1 : 0);
+            e = hipGetLastError();
+            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "map merge launch: %s", hipGetErrorString(e));
+        }
+        if (s == RS_OK && (peaks || doppler_time)) {
+            hipLaunchKernelGGL(k_rd_peak, dim3((unsigned)nframes), dim3(kThreads), 0, st, parts, pw, groups, Ns, L,
+                               rpb, vpb, peaks, doppler_time);
+            e = hipGetLastError();
+            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "peak launch: %s", hipGetErrorString(e));
+        }
+    } else {
+        // workspace: the fast-time spectra, the map when not wanted, the
+        // group maxima
+        const int kb = std::min(std::min(16, kGroupElems / L), Ns);
+        const int groups = Ns / kb;
+        const int64_t rows = (int64_t)nframes * C * L;
+        const size_t rf_bytes = (size_t)(rows * Ns) * sizeof(float2);
+        const size_t part_bytes = (size_t)nframes * groups * sizeof(rd_peak_part);
+        const size_t total = up(rf_bytes) + up(pw_bytes) + up(part_bytes);
+        if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
+            return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", total);
+        float2 *rf = reinterpret_cast<float2 *>(ws);
+        float *pw = power ? power : reinterpret_cast<float *>(ws + up(rf_bytes));
+        rd_peak_part *parts = reinterpret_cast<rd_peak_part *>(ws + up(rf_bytes) + up(pw_bytes));
+        const int rpw = std::max(1, 2048 / Ns);
+        const int64_t g1 = (rows + rpw - 1) / rpw;
+        const size_t lds1 = (size_t)(Ns / 2 + rpw * Ns) * sizeof(float2);
+        if (pl->dtype == RS_C128)
+            hipLaunchKernelGGL(k_range_fft<double2>, dim3((unsigned)g1), dim3(kThreads), lds1, st,
+                               reinterpret_cast<const double2 *>(cubes), rf, rows, logn, rpw);
+        else
+            hipLaunchKernelGGL(k_range_fft<float2>, dim3((unsigned)g1), dim3(kThreads), lds1, st,
+                               reinterpret_cast<const float2 *>(cubes), rf, rows, logn, rpw);
         e = hipGetLastError();
-        if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "Doppler launch: %s", hipGetErrorString(e));
-    }
-    if (s == RS_OK && (peaks || doppler_time)) {
-        const float rpb = pl->mu != 0.0 ? (float)(pl->c0 * pl->Fs / (2.0 * pl->mu * Ns)) : 0.f;
-        const float vpb = pl->fc != 0.0 ? (float)(pl->c0 / (2.0 * pl->fc * pl->Tb * L)) : 0.f;
-        hipLaunchKernelGGL(k_rd_peak, dim3((unsigned)nframes), dim3(kThreads), 0, st, parts, pw, groups, Ns, L, rpb,
-                           vpb, peaks, doppler_time);
-        e = hipGetLastError();
-        if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "peak launch: %s", hipGetErrorString(e));
+        if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "range FFT launch: %s", hipGetErrorString(e));
+        if (s == RS_OK) {
+            const size_t lds2 = (size_t)(L / 2 + kb * L) * sizeof(float2);
+            hipLaunchKernelGGL(k_doppler_power, dim3((unsigned)(nframes * groups)), dim3(kThreads), lds2, st, rf,
+                               pw, parts, C, logl, Ns, kb, skip_static ? 1 : 0);
+            e = hipGetLastError();
+            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "Doppler launch: %s", hipGetErrorString(e));
+        }
+        if (s == RS_OK && (peaks || doppler_time)) {
+            hipLaunchKernelGGL(k_rd_peak, dim3((unsigned)nframes), dim3(kThreads), 0, st, parts, pw, groups, Ns, L,
+                               rpb, vpb, peaks, doppler_time);
+            e = hipGetLastError();
+            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "peak launch: %s", hipGetErrorString(e));
+        }
     }
     e = hipFreeAsync(ws, st);
     if (e != hipSuccess && s == RS_OK) s = rs_fail(RS_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));

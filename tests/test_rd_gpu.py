@@ -76,6 +76,63 @@ def test_walk_frames_batch_and_optional_outputs():
     assert np.array_equal(alone, pk)
 
 
+def _random_cubes(plan, F, seed):
+    """Seeded complex Gaussian cubes [F][C][L][Ns] on the device."""
+    import torch
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    cubes = _rs().new_cube(plan, count=F)
+    real = torch.float64 if cubes.dtype == torch.complex128 else torch.float32
+    cubes.copy_(torch.complex(torch.randn(cubes.shape, generator=g, device="cuda:0", dtype=real),
+                              torch.randn(cubes.shape, generator=g, device="cuda:0", dtype=real)))
+    return cubes
+
+
+def check_rd_frames(radar, plan, cubes, frames, skip_static=True):
+    """GPU maps and peaks of a batch against the oracle on a subset of its
+    frames (each frame's map depends on that frame's cube alone)."""
+    rs = _rs()
+    power, dtime, pk = rs.range_doppler(plan, cubes, skip_static=skip_static)
+    host = cubes[frames].cpu().numpy()
+    ref = rd.range_doppler_power(host)
+    got = power[frames].cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"rd power relL2={rel:.3e} over frames {frames}")
+    assert rel <= TOL_POWER
+    kr, dr = rd.peaks(ref, skip_static=skip_static)
+    L = radar.L
+    dt = dtime.cpu().numpy()
+    for j, f in enumerate(frames):
+        k, d = int(pk["range_bin"][f]), int(pk["doppler_bin"][f]) % L
+        if (k, d) != (kr[j], dr[j]):
+            assert ref[j, k, d] >= ref[j, kr[j], dr[j]] * (1 - 10 * TOL_POWER), (f, k, d, kr[j], dr[j])
+        assert pk["power"][f] == pytest.approx(got[j, k, d], rel=1e-6)
+        assert np.array_equal(dt[f], power[f, k, :].cpu().numpy())
+
+
+@pytest.mark.parametrize("L,dtype", [(16, 0), (32, 1), (64, 0), (128, 1)])
+def test_fused_shapes(L, dtype):
+    """Every fast-time-256 shape of the fused path, both input precisions,
+    on seeded random cubes (7 frames of 12 channels)."""
+    rs = _rs()
+    radar = scenes.radar_for(3, 4, 256, L, Fs=10e6, Tb=3 * 40e-6)
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, dtype, max_pixels=16)
+    cubes = _random_cubes(plan, 7, seed=L + dtype)
+    check_rd_frames(radar, plan, cubes, list(range(7)))
+
+
+def test_fused_runs_across_frames():
+    """300 frames: the workgroups' runs of (frame, channel) items start and
+    end inside frames and span up to three of them, so frames are merged
+    from partial maps of up to four workgroups; frames at run boundaries,
+    the first and the last are checked."""
+    rs = _rs()
+    radar = scenes.radar_frame()
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=16)
+    cubes = _random_cubes(plan, 300, seed=11)
+    check_rd_frames(radar, plan, cubes, [0, 1, 2, 13, 149, 150, 151, 298, 299], skip_static=False)
+
+
 def test_unsupported_and_invalid():
     import torch
     rs = _rs()
