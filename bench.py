@@ -38,9 +38,14 @@ FLOP_PLAIN = 8         # one binary64 complex MAC
 # read for a 1 GiB device copy (fetch x 2.0, write x 1.0).  They hold only for
 # the kernel sources they were taken on; any change to those sources turns
 # the figure into null until the counters are taken again.
-TRAFFIC_SOURCES = ("rs_mfma.hip", "rs_device.h", "rs_internal.h")
-TRAFFIC = {"sources_sha256": "61f5ee16fb6491eaee00921fe8ff606a6d097cb718dbecd5dd749c5ee4bfe7a5",
-           "fetch_bytes": 10.90e6, "write_bytes": 67.00e6}
+TRAFFIC = {"sources": ("rs_mfma.hip", "rs_device.h", "rs_internal.h", "rs_split16.h"),
+           "sources_sha256": "e38527d34e41833d95c47c23b1e0ce06461b849efc0bbb15cba394fd0676aa8b",
+           "fetch_bytes": 2.0 * 5299 * 1024, "write_bytes": 65380 * 1024}
+# The same for one rs_range_doppler call on the 100-frame walk (k_rd_fused,
+# k_rd_merge, k_rd_peak summed).
+RD_TRAFFIC = {"sources": ("rs_rd.hip", "rs_fft.h"),
+              "sources_sha256": "d9e75feb8eacbf4fddb437294d0ad54914960664de12c7abbd90d06d0c3ffee5",
+              "fetch_bytes": 2.0 * (158850 + 20524 + 64) * 1024, "write_bytes": (42880 + 12900 + 55) * 1024}
 
 
 # Offered load of the serving leg, frozen so that latencies stay comparable
@@ -49,15 +54,21 @@ TRAFFIC = {"sources_sha256": "61f5ee16fb6491eaee00921fe8ff606a6d097cb718dbecd5dd
 SERVING_RATE = 137.5
 
 
-def measured_traffic():
+def sources_sha256(sources):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2307_09226_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+    return h.hexdigest()
+
+
+def measured_traffic(rec=None):
+    """HBM bytes of a counter record, or None once its sources changed."""
+    rec = TRAFFIC if rec is None else rec
+    if sources_sha256(rec["sources"]) != rec["sources_sha256"]:
         return None
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def tile_of(desc):
@@ -408,12 +419,15 @@ def doppler_time_leg(rs, scenes, dev, timer):
     power = torch.empty((F, radar.Ns, radar.L), dtype=torch.float32, device=dev)
     dtime = torch.empty((F, radar.L), dtype=torch.float32, device=dev)
     peaks = torch.empty(F * rs.RD_PEAK_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    rwall, rper = timed_steps(lambda: rs.rs_range_doppler(plan, cubes, True, power, dtime, peaks), 10, 2)
+    rd_call = lambda: rs.rs_range_doppler(plan, cubes, True, power, dtime, peaks)  # noqa: E731
+    rd_steps = 50
+    rwall, _ = timed_steps(rd_call, rd_steps, 5, events=False)
+    _, rper = timed_steps(rd_call, 20, 0)   # latency pass: an event pair around each call
     torch.cuda.synchronize()
     pk = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=rs.RD_PEAK_DTYPE)
     v_est = pk["velocity_mps"].astype(np.float64)
     err = np.abs(v_est - cw.v_radial)
-    rd_ms = rwall * 1e3 / 10
+    rd_ms = rwall * 1e3 / rd_steps
     # algorithmic bytes: every cube entry read once (complex64), the power
     # map written once (float32)
     rd_bytes = F * radar.C * radar.L * radar.Ns * 8 + F * radar.Ns * radar.L * 4
@@ -453,7 +467,10 @@ def doppler_time_leg(rs, scenes, dev, timer):
             "rd_ms": rd_ms, "rd_p50_ms": pct(rper, 50),
             "rd_algorithmic_bytes": rd_bytes,
             "rd_roofline": {"bound": "hbm", "achieved": rd_bytes / (rd_ms * 1e-3) / 1e9, "peak": 8000.0,
-                            "unit": "GB/s", "frac": rd_bytes / (rd_ms * 1e-3) / 8e12},
+                            "unit": "GB/s", "frac": rd_bytes / (rd_ms * 1e-3) / 8e12,
+                            "time": "whole rs_range_doppler call (3 launches), throughput pass without events",
+                            "traffic": measured_traffic(RD_TRAFFIC),
+                            "traffic_unit": "HBM bytes per call (all launches)"},
             "E_velo_mps": float(np.mean(err)), "max_abs_error_mps": float(err.max()),
             "doppler_bin_mps": float(radar.c0 / (2 * radar.fc * radar.Tb * radar.L)),
             "corr_v_est_v_true": float(np.corrcoef(v_est, cw.v_radial)[0, 1]),

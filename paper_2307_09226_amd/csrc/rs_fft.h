@@ -1,7 +1,6 @@
 // Radix-2 FFT helpers in LDS, float32 data with twiddles from binary64,
 // used by the range-Doppler maps and the NUFFT form.  Every thread of the
-// workgroup must call twiddles and fft_rows / fft_rows_r4 (they contain
-// barriers).
+// workgroup must call twiddles and fft_rows (fft_rows contains barriers).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -20,41 +19,17 @@ static __device__ void twiddles(float2 *tw, int n, double sign)
     }
 }
 
-// In-place radix-2 DIT over `rows` rows of length n = 2^logn, stored with
-// row stride `stride` (n when 0) in LDS, input in bit-reversed order.
-// tw = twiddles of n.
-static __device__ void fft_rows(float2 *x, int rows, int logn, const float2 *tw, int stride = 0)
-{
-    const int n = 1 << logn;
-    const int rs = stride ? stride : n;
-    const int nb = rows * (n >> 1);  // butterflies per stage
-    for (int s = 0; s < logn; ++s) {
-        const int half = 1 << s;
-        const int tstride = (n >> 1) >> s;  // twiddle index step
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const int row = b >> (logn - 1);
-            const int bb = b & ((n >> 1) - 1);
-            const int pos = bb & (half - 1);
-            const int i = ((bb >> s) << (s + 1)) + pos;
-            float2 *r = x + row * rs;
-            const float2 t = cmul(tw[pos * tstride], r[i + half]);
-            const float2 u = r[i];
-            r[i] = make_float2(u.x + t.x, u.y + t.y);
-            r[i + half] = make_float2(u.x - t.x, u.y - t.y);
-        }
-        __syncthreads();
-    }
-}
-
 __device__ __forceinline__ int bitrev(int v, int logn) { return (int)(__brev((unsigned)v) >> (32 - logn)); }
 
-// fft_rows with two radix-2 stages per pass: a thread takes the four
-// elements (i, i+h, i+2h, i+3h) of a block of 4h, applies stage s to the
-// pairs (i, i+h) and (i+2h, i+3h) and stage s+1 to (i, i+2h) and
-// (i+h, i+3h) -- the operations of fft_rows in the same order, so the
-// result is bit for bit the same, with half the barriers and LDS round
-// trips.  An odd number of stages ends with one radix-2 stage.
-static __device__ void fft_rows_r4(float2 *x, int rows, int logn, const float2 *tw, int stride = 0)
+// In-place radix-2 DIT over `rows` rows of length n = 2^logn, stored with
+// row stride `stride` (n when 0) in LDS, input in bit-reversed order;
+// tw = twiddles of n.  The stages are taken two at a time: a thread takes
+// the four elements (i, i+h, i+2h, i+3h) of a block of 4h, applies stage s
+// to the pairs (i, i+h) and (i+2h, i+3h) and stage s+1 to (i, i+2h) and
+// (i+h, i+3h), the butterflies of the one-stage-at-a-time form in the same
+// order with half the barriers and LDS round trips.  An odd number of
+// stages ends with one radix-2 stage.
+static __device__ void fft_rows(float2 *x, int rows, int logn, const float2 *tw, int stride = 0)
 {
     const int n = 1 << logn;
     const int rs = stride ? stride : n;

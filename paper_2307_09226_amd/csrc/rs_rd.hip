@@ -325,7 +325,7 @@ __global__ __launch_bounds__((rd_fused_shape<D2, RPT>::T)) void k_rd_fused(const
 #pragma unroll
     for (int r = 0; r < PF; ++r)
 #pragma unroll
-        for (int n1 = 0; n1 < kFR; ++n1) pre[r][n1] = load_c(tile + min(i0, i1 - 1) * (int64_t)(L * kFNs) + r * (L / RPT) * kFNs + kFR * n1);
+        for (int n1 = 0; n1 < kFR; ++n1) pre[r][n1] = load_c(tile + i0 * (int64_t)(L * kFNs) + r * (L / RPT) * kFNs + kFR * n1);
     for (int64_t it = i0; it < i1; ++it) {
         const IT *src = tile + it * (int64_t)(L * kFNs);
         float2 v[RPT][kFR];
@@ -366,7 +366,10 @@ __global__ __launch_bounds__((rd_fused_shape<D2, RPT>::T)) void k_rd_fused(const
                 for (int k2 = 0; k2 < kFR / 2; ++k2)
                     buf[(q + kFR * k2) * P + (g ^ sig) + r * (L / RPT)] = v[r][h * (kFR / 2) + k2];
             if (h == 1) {
-                const IT *nsrc = tile + min(it + 1, i1 - 1) * (int64_t)(L * kFNs);
+                // after the run's last item the load is a dummy one of item
+                // 0's rows, which every workgroup shares through L2 (a
+                // branch here would cost registers)
+                const IT *nsrc = tile + (it + 1 < i1 ? it + 1 : 0) * (int64_t)(L * kFNs);
 #pragma unroll
                 for (int r = 0; r < PF; ++r)
 #pragma unroll
