@@ -19,7 +19,7 @@
 //                read back from LDS written in place), |.|^2 accumulated in
 //                registers over the run's channels; one partial map per
 //                (workgroup, frame) written at the run's frame boundaries
-//   k_rd_merge   per (frame, block of 1024 cells): the partial maps of the
+//   k_rd_merge   per (frame, block of 4096 cells): the partial maps of the
 //                workgroups that cover the frame summed in workgroup order
 //                -> power, and the block's maximum
 //   k_rd_peak    per frame: the maximum over the blocks, its range and
@@ -166,7 +166,7 @@ constexpr int kFNs = 256;                 // fast-time length of the fused path
 constexpr int kFR = 16;                   // 256 = 16 x 16
 constexpr int kFHalf = kFNs / 2;          // range bins per slow-time half
 constexpr int kFX1 = kFR * (kFR + 1);     // one row of the fast-time transpose (padded, = 16 mod 32)
-constexpr int kMergeCells = 1024;         // cells per k_rd_merge workgroup
+constexpr int kMergeCells = 4096;         // cells per k_rd_merge workgroup (256 threads, 4 float4 each)
 constexpr int kFusedRows = 4;             // tile rows a thread holds (64 entries)
 
 // cos(2 pi m / 16), m taken modulo 16
@@ -431,37 +431,47 @@ __global__ __launch_bounds__((rd_fused_shape<D2, RPT>::T)) void k_rd_fused(const
     }
 }
 
-// Per (frame, block of 1024 cells): the frame's partial maps summed in
+// Per (frame, block of 4096 cells): the frame's partial maps summed in
 // workgroup order -> power, and the block's maximum (smallest cell index on
 // ties; d = 0 skipped when skip_static).
 __global__ __launch_bounds__(256) void k_rd_merge(const float *__restrict__ slots, float *__restrict__ power,
                                                  rd_peak_part *parts, int C, int64_t nitems, int W, int J,
                                                  int cells, int L, int skip_static)
 {
+    constexpr int V = kMergeCells / (4 * 256);   // float4 per thread
     const int nblk = cells / kMergeCells;
     const int64_t f = blockIdx.x / nblk;
     const int b = blockIdx.x % nblk;
-    const int e = b * kMergeCells + threadIdx.x * 4;
     const int64_t wlo = ((f * C + 1) * W - 1) / nitems, whi = ((f * C + C) * W - 1) / nitems;
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 s[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) s[v] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int64_t w = wlo; w <= whi; ++w) {
         const int64_t first = (w * nitems / W) / C;
-        const float4 p = *reinterpret_cast<const float4 *>(slots + (w * J + (f - first)) * (int64_t)cells + e);
-        s.x += p.x;
-        s.y += p.y;
-        s.z += p.z;
-        s.w += p.w;
+        const float *src = slots + (w * J + (f - first)) * (int64_t)cells + b * kMergeCells + threadIdx.x * 4;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const float4 p = *reinterpret_cast<const float4 *>(src + v * 1024);
+            s[v].x += p.x;
+            s[v].y += p.y;
+            s[v].z += p.z;
+            s[v].w += p.w;
+        }
     }
-    *reinterpret_cast<float4 *>(power + f * (int64_t)cells + e) = s;
-    const float vals[4] = {s.x, s.y, s.z, s.w};
     float best = -1.f;
     int bidx = -1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int c = e + i;
-        if (!(skip_static && (c & (L - 1)) == 0) && vals[i] > best) {
-            best = vals[i];
-            bidx = c;
+    for (int v = 0; v < V; ++v) {
+        const int e = b * kMergeCells + v * 1024 + threadIdx.x * 4;
+        *reinterpret_cast<float4 *>(power + f * (int64_t)cells + e) = s[v];
+        const float vals[4] = {s[v].x, s[v].y, s[v].z, s[v].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = e + i;
+            if (!(skip_static && (c & (L - 1)) == 0) && vals[i] > best) {
+                best = vals[i];
+                bidx = c;
+            }
         }
     }
     __shared__ float rv[256];
@@ -635,7 +645,7 @@ extern "C" rs_status rs_range_doppler(rs_plan *pl, const void *cubes, int32_t nf
                                  : launch_fused_l<float2>(L, cubes, slots, C, nitems, (int)W, (int)J, st);
         if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "fused range-Doppler launch: %s", hipGetErrorString(e));
         if (s == RS_OK) {
-            hipLaunchKernelGGL(k_rd_merge, dim3((unsigned)(nframes * groups)), dim3(kMergeCells / 4), 0, st, slots,
+            hipLaunchKernelGGL(k_rd_merge, dim3((unsigned)(nframes * groups)), dim3(256), 0, st, slots,
                                pw, parts, C, nitems, (int)W, (int)J, (int)cells, L, skip_static ? 1 : 0);
             e = hipGetLastError();
             if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "map merge launch: %s", hipGetErrorString(e));
