@@ -44,8 +44,8 @@ TRAFFIC = {"sources": ("rs_mfma.hip", "rs_device.h", "rs_internal.h", "rs_split1
 # The same for one rs_range_doppler call on the 100-frame walk (k_rd_fused,
 # k_rd_merge, k_rd_peak summed).
 RD_TRAFFIC = {"sources": ("rs_rd.hip", "rs_fft.h"),
-              "sources_sha256": "d9e75feb8eacbf4fddb437294d0ad54914960664de12c7abbd90d06d0c3ffee5",
-              "fetch_bytes": 2.0 * (158850 + 20524 + 64) * 1024, "write_bytes": (42880 + 12900 + 55) * 1024}
+              "sources_sha256": "98ffdb4097d7a99dcd28b64627907c0dbe6f33edb9ee8af9f917b6f97c7d2b27",
+              "fetch_bytes": 2.0 * (158862 + 20530 + 52) * 1024, "write_bytes": (42881 + 12825 + 55) * 1024}
 
 
 # Offered load of the serving leg, frozen so that latencies stay comparable
