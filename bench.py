@@ -41,11 +41,11 @@ FLOP_PLAIN = 8         # one binary64 complex MAC
 TRAFFIC = {"sources": ("rs_mfma.hip", "rs_device.h", "rs_internal.h", "rs_split16.h"),
            "sources_sha256": "e38527d34e41833d95c47c23b1e0ce06461b849efc0bbb15cba394fd0676aa8b",
            "fetch_bytes": 2.0 * 5299 * 1024, "write_bytes": 65380 * 1024}
-# The same for one rs_range_doppler call on the 100-frame walk (k_rd_fused,
+# The same for one rs_range_doppler_ws call on the 100-frame walk (k_rd_fused,
 # k_rd_merge, k_rd_peak summed).
 RD_TRAFFIC = {"sources": ("rs_rd.hip", "rs_fft.h"),
-              "sources_sha256": "98ffdb4097d7a99dcd28b64627907c0dbe6f33edb9ee8af9f917b6f97c7d2b27",
-              "fetch_bytes": 2.0 * (158862 + 20530 + 52) * 1024, "write_bytes": (42881 + 12825 + 55) * 1024}
+              "sources_sha256": "946f817b4e88a0b599a22421c1a2ffcda6df66330e59c9ae97daa3e52f74d8f3",
+              "fetch_bytes": 2.0 * (158861 + 20530 + 52) * 1024, "write_bytes": (42880 + 12825 + 55) * 1024}
 
 
 # Offered load of the serving leg, frozen so that latencies stay comparable
@@ -419,7 +419,8 @@ def doppler_time_leg(rs, scenes, dev, timer):
     power = torch.empty((F, radar.Ns, radar.L), dtype=torch.float32, device=dev)
     dtime = torch.empty((F, radar.L), dtype=torch.float32, device=dev)
     peaks = torch.empty(F * rs.RD_PEAK_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-    rd_call = lambda: rs.rs_range_doppler(plan, cubes, True, power, dtime, peaks)  # noqa: E731
+    rd_ws = torch.empty(rs.rs_range_doppler_workspace_bytes(plan, F, True), dtype=torch.uint8, device=dev)
+    rd_call = lambda: rs.rs_range_doppler_ws(plan, cubes, True, power, dtime, peaks, rd_ws)  # noqa: E731
     rd_steps = 50
     rwall, _ = timed_steps(rd_call, rd_steps, 5, events=False)
     _, rper = timed_steps(rd_call, 20, 0)   # latency pass: an event pair around each call
@@ -452,7 +453,7 @@ def doppler_time_leg(rs, scenes, dev, timer):
     def pipeline():
         fr = rs.rs_render_scenes(structs, g, g, noise, dev, out=pix)
         rs.rs_beat_synthesize_batch(plan, fr, cubes)
-        rs.rs_range_doppler(plan, cubes, True, power, dtime, peaks)
+        rd_call()
     pwall, _ = timed_steps(pipeline, 3, 1)
     torch.cuda.synchronize()
     pk2 = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=rs.RD_PEAK_DTYPE)
@@ -468,7 +469,8 @@ def doppler_time_leg(rs, scenes, dev, timer):
             "rd_algorithmic_bytes": rd_bytes,
             "rd_roofline": {"bound": "hbm", "achieved": rd_bytes / (rd_ms * 1e-3) / 1e9, "peak": 8000.0,
                             "unit": "GB/s", "frac": rd_bytes / (rd_ms * 1e-3) / 8e12,
-                            "time": "whole rs_range_doppler call (3 launches), throughput pass without events",
+                            "time": "whole rs_range_doppler_ws call (3 launches, workspace allocated once), "
+                                    "throughput pass without events",
                             "traffic": measured_traffic(RD_TRAFFIC),
                             "traffic_unit": "HBM bytes per call (all launches)"},
             "E_velo_mps": float(np.mean(err)), "max_abs_error_mps": float(err.max()),

@@ -466,14 +466,34 @@ typedef struct {
  *   doppler_time  float32 [nframes][L]      power[k_peak][.] of each frame:
  *                                           its velocity spectrum at the peak
  *   peaks         rs_rd_peak [nframes]
- * Arithmetic in float32 (radix-2 FFTs in LDS, twiddles from binary64).
+ * Arithmetic in float32 with twiddles from binary64: for Ns = 256 and
+ * L in 16..128 each channel's 2-D FFT runs in registers and LDS within one
+ * workgroup and the channels' power is summed in registers (partial maps
+ * of the workgroups that share a frame are added in a fixed order); other
+ * shapes take two passes of radix-2 LDS FFTs.  Deterministic.
  * Needs Ns and L powers of two, Ns <= 4096, L <= 1024 (else
- * RS_E_UNSUPPORTED).  Temporary device memory (8 bytes per cube entry) is
- * allocated and freed in stream order.
+ * RS_E_UNSUPPORTED).  Temporary device memory
+ * (rs_range_doppler_workspace_bytes) is allocated and freed in stream
+ * order.
  * Errors: RS_E_INVALID (NULL plan or cubes with nframes > 0, nframes < 0),
  * RS_E_UNSUPPORTED, RS_E_NOMEM, RS_E_DEVICE.  nframes = 0 does nothing. */
 rs_status rs_range_doppler(rs_plan *plan, const void *cubes, int32_t nframes, int32_t skip_static,
                            float *power, float *doppler_time, rs_rd_peak *peaks, void *hip_stream);
+
+/* Device bytes of temporary memory that rs_range_doppler uses for
+ * `nframes` cubes of `plan`, with (power_given = 1) or without a caller's
+ * power map; 0 for nframes <= 0 or a NULL plan. */
+size_t rs_range_doppler_workspace_bytes(const rs_plan *plan, int32_t nframes, int32_t power_given);
+
+/* rs_range_doppler with the temporary memory in `workspace` (device memory
+ * of workspace_bytes >= rs_range_doppler_workspace_bytes(plan, nframes,
+ * power != NULL), 256-byte aligned, owned by the caller and not used by
+ * anything else until the stream reaches the end of the call): no
+ * allocation.  Same results bit for bit.  Errors: as rs_range_doppler, and
+ * RS_E_INVALID for a NULL, misaligned or too small workspace. */
+rs_status rs_range_doppler_ws(rs_plan *plan, const void *cubes, int32_t nframes, int32_t skip_static,
+                              float *power, float *doppler_time, rs_rd_peak *peaks, void *workspace,
+                              size_t workspace_bytes, void *hip_stream);
 
 /* --------------------------------------------------------- kernel timer -- */
 /* Per-launch timing of the main (contraction) kernel with HIP events, for

@@ -599,77 +599,88 @@ hipError_t launch_fused_l(int L, const void *cubes, float *slots, int C, int64_t
 
 }  // namespace
 
-extern "C" rs_status rs_range_doppler(rs_plan *pl, const void *cubes, int32_t nframes, int32_t skip_static,
-                                      float *power, float *doppler_time, rs_rd_peak *peaks, void *stream)
+namespace {
+
+// Workspace of one call, in 256-byte aligned pieces.  Fused path: the
+// partial maps [W][J][cells], the map when the caller wants none, the block
+// maxima.  Two-pass path: the float2 fast-time spectra, the map when the
+// caller wants none, the group maxima.
+struct rd_layout {
+    bool fused = false;
+    int64_t W = 0, J = 0, nitems = 0;
+    int groups = 0, kb = 0;
+    size_t mid = 0, pw = 0, parts = 0, total = 0;   // byte offsets / sizes
+};
+
+rd_layout rd_plan_layout(const rs_plan *pl, int64_t nframes, bool power_given)
+{
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    rd_layout y;
+    const int Ns = pl->Ns, L = pl->L, C = pl->C;
+    const int64_t cells = (int64_t)Ns * L;
+    y.fused = Ns == kFNs && L >= 16 && L <= 128;
+    size_t mid_bytes;
+    if (y.fused) {
+        y.nitems = nframes * C;
+        y.W = rd_fused_workgroups(nframes, C, pl->ncu);
+        const int64_t per = (y.nitems + y.W - 1) / y.W;
+        y.J = (per - 1 + C - 1) / C + 1;   // frames a run of `per` items can touch
+        y.groups = (int)(cells / kMergeCells);
+        mid_bytes = (size_t)(y.W * y.J * cells) * sizeof(float);
+    } else {
+        y.kb = std::min(std::min(16, kGroupElems / L), Ns);
+        y.groups = Ns / y.kb;
+        mid_bytes = (size_t)(nframes * C * L * Ns) * sizeof(float2);
+    }
+    const size_t pw_bytes = power_given ? 0 : (size_t)(nframes * cells) * sizeof(float);
+    const size_t part_bytes = (size_t)nframes * y.groups * sizeof(rd_peak_part);
+    y.mid = 0;
+    y.pw = up(mid_bytes);
+    y.parts = y.pw + up(pw_bytes);
+    y.total = y.parts + up(part_bytes);
+    return y;
+}
+
+// Argument checks of both entry points; nframes = 0 passes (nothing to do).
+rs_status rd_check(const rs_plan *pl, const void *cubes, int32_t nframes, int *logn, int *logl)
 {
     if (!pl) return rs_fail(RS_E_INVALID, "plan is NULL");
     if (nframes < 0) return rs_fail(RS_E_INVALID, "nframes < 0");
     if (nframes == 0) return RS_OK;
     if (!cubes) return rs_fail(RS_E_INVALID, "cubes is NULL");
-    const int logn = ilog2_exact(pl->Ns), logl = ilog2_exact(pl->L);
-    if (logn < 1 || logl < 1 || pl->Ns > 4096 || pl->L > 1024)
+    *logn = ilog2_exact(pl->Ns);
+    *logl = ilog2_exact(pl->L);
+    if (*logn < 1 || *logl < 1 || pl->Ns > 4096 || pl->L > 1024)
         return rs_fail(RS_E_UNSUPPORTED, "range-Doppler maps need Ns and L powers of two, 2 <= Ns <= 4096, "
                                          "2 <= L <= 1024 (got Ns = %d, L = %d)", pl->Ns, pl->L);
-    device_guard g(pl->device);
-    if (g.st != RS_OK) return g.st;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return RS_OK;
+}
 
+// The launches of one call on `st` with the workspace `ws` laid out as y.
+rs_status rd_run(const rs_plan *pl, const rd_layout &y, const void *cubes, int32_t nframes, int32_t skip_static,
+                 float *power, float *doppler_time, rs_rd_peak *peaks, char *ws, int logn, int logl,
+                 hipStream_t st)
+{
     const int Ns = pl->Ns, L = pl->L, C = pl->C;
     const int64_t cells = (int64_t)Ns * L;
-    const bool fused = Ns == kFNs && L >= 16 && L <= 128;
-    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const float rpb = pl->mu != 0.0 ? (float)(pl->c0 * pl->Fs / (2.0 * pl->mu * Ns)) : 0.f;
     const float vpb = pl->fc != 0.0 ? (float)(pl->c0 / (2.0 * pl->fc * pl->Tb * L)) : 0.f;
-    const size_t pw_bytes = power ? 0 : (size_t)(nframes * cells) * sizeof(float);
-
-    rs_status s = RS_OK;
+    float *pw = power ? power : reinterpret_cast<float *>(ws + y.pw);
+    rd_peak_part *parts = reinterpret_cast<rd_peak_part *>(ws + y.parts);
     hipError_t e;
-    char *ws = nullptr;
-    if (fused) {
-        // workspace: the partial maps [W][J][cells], the map when not
-        // wanted, the block maxima
-        const int64_t nitems = (int64_t)nframes * C;
-        const int64_t W = rd_fused_workgroups(nframes, C, pl->ncu);
-        const int64_t per = (nitems + W - 1) / W;
-        const int64_t J = (per - 1 + C - 1) / C + 1;   // frames a run of `per` items can touch
-        const int groups = (int)(cells / kMergeCells);
-        const size_t slot_bytes = (size_t)(W * J * cells) * sizeof(float);
-        const size_t part_bytes = (size_t)nframes * groups * sizeof(rd_peak_part);
-        const size_t total = up(slot_bytes) + up(pw_bytes) + up(part_bytes);
-        if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
-            return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", total);
-        float *slots = reinterpret_cast<float *>(ws);
-        float *pw = power ? power : reinterpret_cast<float *>(ws + up(slot_bytes));
-        rd_peak_part *parts = reinterpret_cast<rd_peak_part *>(ws + up(slot_bytes) + up(pw_bytes));
-        e = pl->dtype == RS_C128 ? launch_fused_l<double2>(L, cubes, slots, C, nitems, (int)W, (int)J, st)
-                                 : launch_fused_l<float2>(L, cubes, slots, C, nitems, (int)W, (int)J, st);
-        if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "fused range-Doppler launch: %s", hipGetErrorString(e));
-        if (s == RS_OK) {
-            hipLaunchKernelGGL(k_rd_merge, dim3((unsigned)(nframes * groups)), dim3(256), 0, st, slots,
-                               pw, parts, C, nitems, (int)W, (int)J, (int)cells, L, skip_static ? 1 : 0);
-            e = hipGetLastError();
-            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "map merge launch: %s", hipGetErrorString(e));
-        }
-        if (s == RS_OK && (peaks || doppler_time)) {
-            hipLaunchKernelGGL(k_rd_peak, dim3((unsigned)nframes), dim3(kThreads), 0, st, parts, pw, groups, Ns, L,
-                               rpb, vpb, peaks, doppler_time);
-            e = hipGetLastError();
-            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "peak launch: %s", hipGetErrorString(e));
-        }
+    if (y.fused) {
+        float *slots = reinterpret_cast<float *>(ws + y.mid);
+        e = pl->dtype == RS_C128
+                ? launch_fused_l<double2>(L, cubes, slots, C, y.nitems, (int)y.W, (int)y.J, st)
+                : launch_fused_l<float2>(L, cubes, slots, C, y.nitems, (int)y.W, (int)y.J, st);
+        if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "fused range-Doppler launch: %s", hipGetErrorString(e));
+        hipLaunchKernelGGL(k_rd_merge, dim3((unsigned)(nframes * y.groups)), dim3(256), 0, st, slots, pw, parts, C,
+                           y.nitems, (int)y.W, (int)y.J, (int)cells, L, skip_static ? 1 : 0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "map merge launch: %s", hipGetErrorString(e));
     } else {
-        // workspace: the fast-time spectra, the map when not wanted, the
-        // group maxima
-        const int kb = std::min(std::min(16, kGroupElems / L), Ns);
-        const int groups = Ns / kb;
+        float2 *rf = reinterpret_cast<float2 *>(ws + y.mid);
         const int64_t rows = (int64_t)nframes * C * L;
-        const size_t rf_bytes = (size_t)(rows * Ns) * sizeof(float2);
-        const size_t part_bytes = (size_t)nframes * groups * sizeof(rd_peak_part);
-        const size_t total = up(rf_bytes) + up(pw_bytes) + up(part_bytes);
-        if (hipMallocAsync(reinterpret_cast<void **>(&ws), total, st) != hipSuccess)
-            return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", total);
-        float2 *rf = reinterpret_cast<float2 *>(ws);
-        float *pw = power ? power : reinterpret_cast<float *>(ws + up(rf_bytes));
-        rd_peak_part *parts = reinterpret_cast<rd_peak_part *>(ws + up(rf_bytes) + up(pw_bytes));
         const int rpw = std::max(1, 2048 / Ns);
         const int64_t g1 = (rows + rpw - 1) / rpw;
         const size_t lds1 = (size_t)(Ns / 2 + rpw * Ns) * sizeof(float2);
@@ -680,22 +691,63 @@ extern "C" rs_status rs_range_doppler(rs_plan *pl, const void *cubes, int32_t nf
             hipLaunchKernelGGL(k_range_fft<float2>, dim3((unsigned)g1), dim3(kThreads), lds1, st,
                                reinterpret_cast<const float2 *>(cubes), rf, rows, logn, rpw);
         e = hipGetLastError();
-        if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "range FFT launch: %s", hipGetErrorString(e));
-        if (s == RS_OK) {
-            const size_t lds2 = (size_t)(L / 2 + kb * L) * sizeof(float2);
-            hipLaunchKernelGGL(k_doppler_power, dim3((unsigned)(nframes * groups)), dim3(kThreads), lds2, st, rf,
-                               pw, parts, C, logl, Ns, kb, skip_static ? 1 : 0);
-            e = hipGetLastError();
-            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "Doppler launch: %s", hipGetErrorString(e));
-        }
-        if (s == RS_OK && (peaks || doppler_time)) {
-            hipLaunchKernelGGL(k_rd_peak, dim3((unsigned)nframes), dim3(kThreads), 0, st, parts, pw, groups, Ns, L,
-                               rpb, vpb, peaks, doppler_time);
-            e = hipGetLastError();
-            if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "peak launch: %s", hipGetErrorString(e));
-        }
+        if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "range FFT launch: %s", hipGetErrorString(e));
+        const size_t lds2 = (size_t)(L / 2 + y.kb * L) * sizeof(float2);
+        hipLaunchKernelGGL(k_doppler_power, dim3((unsigned)(nframes * y.groups)), dim3(kThreads), lds2, st, rf, pw,
+                           parts, C, logl, Ns, y.kb, skip_static ? 1 : 0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "Doppler launch: %s", hipGetErrorString(e));
     }
-    e = hipFreeAsync(ws, st);
+    if (peaks || doppler_time) {
+        hipLaunchKernelGGL(k_rd_peak, dim3((unsigned)nframes), dim3(kThreads), 0, st, parts, pw, y.groups, Ns, L, rpb,
+                           vpb, peaks, doppler_time);
+        e = hipGetLastError();
+        if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "peak launch: %s", hipGetErrorString(e));
+    }
+    return RS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t rs_range_doppler_workspace_bytes(const rs_plan *pl, int32_t nframes, int32_t power_given)
+{
+    if (!pl || nframes <= 0) return 0;
+    return rd_plan_layout(pl, nframes, power_given != 0).total;
+}
+
+extern "C" rs_status rs_range_doppler(rs_plan *pl, const void *cubes, int32_t nframes, int32_t skip_static,
+                                      float *power, float *doppler_time, rs_rd_peak *peaks, void *stream)
+{
+    int logn = 0, logl = 0;
+    const rs_status c = rd_check(pl, cubes, nframes, &logn, &logl);
+    if (c != RS_OK || nframes == 0) return c;
+    device_guard g(pl->device);
+    if (g.st != RS_OK) return g.st;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const rd_layout y = rd_plan_layout(pl, nframes, power != nullptr);
+    char *ws = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&ws), y.total, st) != hipSuccess)
+        return rs_fail(RS_E_NOMEM, "stream-ordered workspace allocation of %zu bytes failed", y.total);
+    rs_status s = rd_run(pl, y, cubes, nframes, skip_static, power, doppler_time, peaks, ws, logn, logl, st);
+    const hipError_t e = hipFreeAsync(ws, st);
     if (e != hipSuccess && s == RS_OK) s = rs_fail(RS_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
     return s;
+}
+
+extern "C" rs_status rs_range_doppler_ws(rs_plan *pl, const void *cubes, int32_t nframes, int32_t skip_static,
+                                         float *power, float *doppler_time, rs_rd_peak *peaks, void *workspace,
+                                         size_t workspace_bytes, void *stream)
+{
+    int logn = 0, logl = 0;
+    const rs_status c = rd_check(pl, cubes, nframes, &logn, &logl);
+    if (c != RS_OK || nframes == 0) return c;
+    const rd_layout y = rd_plan_layout(pl, nframes, power != nullptr);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return rs_fail(RS_E_INVALID, "workspace is NULL or not 256-byte aligned");
+    if (workspace_bytes < y.total)
+        return rs_fail(RS_E_INVALID, "workspace of %zu bytes, %zu needed", workspace_bytes, y.total);
+    device_guard g(pl->device);
+    if (g.st != RS_OK) return g.st;
+    return rd_run(pl, y, cubes, nframes, skip_static, power, doppler_time, peaks, static_cast<char *>(workspace),
+                  logn, logl, reinterpret_cast<hipStream_t>(stream));
 }

@@ -124,6 +124,9 @@ SIGNATURES = {
     "rs_session_inject_failure": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "rs_session_inject_device_error": (ctypes.c_int, [_VP]),
     "rs_range_doppler": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP]),
+    "rs_range_doppler_ws": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP, _VP,
+                                           ctypes.c_size_t, _VP]),
+    "rs_range_doppler_workspace_bytes": (ctypes.c_size_t, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "rs_render_scenes": (ctypes.c_int, [ctypes.POINTER(rs_scene), ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "rs_kernel_timer_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP)]),
@@ -353,6 +356,24 @@ def rs_range_doppler(plan: Plan, cubes, skip_static: bool = True, power=None, do
                                 _ptr(doppler_time) if doppler_time is not None else None,
                                 _ptr(peaks) if peaks is not None else None,
                                 _stream_handle(stream)))
+
+
+def rs_range_doppler_workspace_bytes(plan: Plan, nframes: int, power_given: bool = True) -> int:
+    return int(lib.rs_range_doppler_workspace_bytes(plan.handle, int(nframes), 1 if power_given else 0))
+
+
+def rs_range_doppler_ws(plan: Plan, cubes, skip_static: bool, power, doppler_time, peaks, workspace,
+                        stream=None):
+    """rs_range_doppler with a caller's device workspace (a uint8 tensor of
+    at least rs_range_doppler_workspace_bytes): nothing is allocated."""
+    nframes = 1 if cubes.dim() == 3 else int(cubes.shape[0])
+    _check(lib.rs_range_doppler_ws(plan.handle, _ptr(cubes), nframes, 1 if skip_static else 0,
+                                   _ptr(power) if power is not None else None,
+                                   _ptr(doppler_time) if doppler_time is not None else None,
+                                   _ptr(peaks) if peaks is not None else None,
+                                   _ptr(workspace) if workspace is not None else None,
+                                   int(workspace.numel() * workspace.element_size()) if workspace is not None else 0,
+                                   _stream_handle(stream)))
 
 
 def range_doppler(plan: Plan, cubes, skip_static: bool = True, stream=None):

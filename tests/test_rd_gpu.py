@@ -133,6 +133,42 @@ def test_fused_runs_across_frames():
     check_rd_frames(radar, plan, cubes, [0, 1, 2, 13, 149, 150, 151, 298, 299], skip_static=False)
 
 
+@pytest.mark.parametrize("L", [64, 128])
+def test_workspace_variant_matches(L):
+    """rs_range_doppler_ws with a caller's workspace gives the bits of
+    rs_range_doppler, with and without a power map; short or misaligned
+    workspaces are refused."""
+    import torch
+    rs = _rs()
+    radar = scenes.radar_for(3, 4, 256, L, Fs=10e6, Tb=3 * 40e-6)
+    plan = rs.rs_cube_plan(radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=16)
+    F = 9
+    cubes = _random_cubes(plan, F, seed=5)
+    power, dtime, pk = rs.range_doppler(plan, cubes, skip_static=True)
+    need = rs.rs_range_doppler_workspace_bytes(plan, F, True)
+    need_np = rs.rs_range_doppler_workspace_bytes(plan, F, False)
+    assert need_np == need + (F * radar.Ns * L * 4 + 255) // 256 * 256
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda:0")
+    p2 = torch.empty_like(power)
+    d2 = torch.empty_like(dtime)
+    k2 = torch.empty(F * rs.RD_PEAK_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+    rs.rs_range_doppler_ws(plan, cubes, True, p2, d2, k2, ws)
+    assert torch.equal(p2, power) and torch.equal(d2, dtime)
+    assert np.array_equal(np.frombuffer(k2.cpu().numpy().tobytes(), dtype=rs.RD_PEAK_DTYPE), pk)
+    # without a power map the workspace holds it
+    ws2 = torch.empty(need_np, dtype=torch.uint8, device="cuda:0")
+    k3 = torch.zeros_like(k2)
+    rs.rs_range_doppler_ws(plan, cubes, True, None, None, k3, ws2)
+    assert torch.equal(k3, k2)
+    code = rs.lib.rs_range_doppler_ws(plan.handle, cubes.data_ptr(), F, 1, p2.data_ptr(), None, None,
+                                      ws.data_ptr(), need - 1, None)
+    assert code == rs.RS_E_INVALID and "needed" in rs.rs_last_error()
+    code = rs.lib.rs_range_doppler_ws(plan.handle, cubes.data_ptr(), F, 1, p2.data_ptr(), None, None,
+                                      ws.data_ptr() + 8, need, None)
+    assert code == rs.RS_E_INVALID and "aligned" in rs.rs_last_error()
+    torch.cuda.synchronize()
+
+
 def test_unsupported_and_invalid():
     import torch
     rs = _rs()
