@@ -44,7 +44,7 @@ TRAFFIC = {"sources": ("rs_mfma.hip", "rs_device.h", "rs_internal.h", "rs_split1
 # The same for one rs_range_doppler_ws call on the 100-frame walk (k_rd_fused,
 # k_rd_merge, k_rd_peak summed).
 RD_TRAFFIC = {"sources": ("rs_rd.hip", "rs_fft.h"),
-              "sources_sha256": "946f817b4e88a0b599a22421c1a2ffcda6df66330e59c9ae97daa3e52f74d8f3",
+              "sources_sha256": "95099bdcdb4bfc8754d0a938c3fa665fedb0f6060603a9d34e880fcf3a09d309",
               "fetch_bytes": 2.0 * (158861 + 20530 + 52) * 1024, "write_bytes": (42880 + 12825 + 55) * 1024}
 
 

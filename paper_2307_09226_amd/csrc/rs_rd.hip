@@ -577,8 +577,9 @@ hipError_t launch_fused(const void *cubes, float *slots, int C, int64_t nitems, 
 {
     constexpr int RPT = kFusedRows;
     using S = rd_fused_shape<D2, RPT>;
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rd_fused<D2, RPT, IT>),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds);
+    // set on every launch: the attribute belongs to the device current now
+    const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rd_fused<D2, RPT, IT>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds);
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_rd_fused<D2, RPT, IT>), dim3((unsigned)W), dim3(S::T), S::lds, st,
                        reinterpret_cast<const IT *>(cubes), slots, C, nitems, W, J);
