@@ -89,13 +89,14 @@ __device__ __forceinline__ void pin(float &u, float &w) { rs_pin(u, w); }
 __device__ __forceinline__ void rot(float &u, float &w, float rx, float ry) { rs_rot(u, w, rx, ry); }
 
 // Both column arrangements of a D entry u + j w, real (u, w) and imaginary
-// (-w, u), each split into hi and lo.
+// (-w, u), each split into hi and lo; the imaginary pair is the real one
+// times j (rs_jmul), which saves a conversion and two mixed multiply-adds.
 __device__ __forceinline__ void d_split(float u, float w, half2v &hre, half2v &him, half2v &lre, half2v &lim)
 {
     hre = hi2(u, w);
-    him = hi2(-w, u);
     lre = lo2(u, w, hre);
-    lim = lo2(-w, u, him);
+    him = rs_jmul(hre);
+    lim = rs_jmul(lre);
 }
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -251,16 +252,21 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         };
 
         // One F pixel (matrix step ft, pixel j of the lane's group of four)
-        // of step st for every row block of this lane -> hi and lo operands.
+        // of step st for every row block of this lane -> hi and lo operands,
+        // from the pixel's phase parameters (psi_f, b).
         struct fops {
             half8 h[2][RB], l[2][RB];
         };
-        auto gen_f_pixel = [&](int st, int ft, int j, fops &fo) {
-            const pix_par &pf = sPar[(st / kSPB) & 1][(st % kSPB) * kKP + 8 * ft + 4 * g + j];
-            const float f = frac32(__builtin_fma(pf.b, nrow0, pf.psi_f));
+        auto gen_f_reg = [&](int st, int ft, int j, double psi_f, double b, fops &fo) {
+            const float f = frac32(__builtin_fma(b, nrow0, psi_f));
             float cv = __builtin_amdgcn_cosf(f);
             float sv = __builtin_amdgcn_sinf(f);
-            const float ex = pf.e32x, ey = pf.e32y;
+            float ex = 0.f, ey = 0.f;
+            if constexpr (RB > 1) {
+                const pix_par &pf = sPar[(st / kSPB) & 1][(st % kSPB) * kKP + 8 * ft + 4 * g + j];
+                ex = pf.e32x;
+                ey = pf.e32y;
+            }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const half2v h = hi2(cv, sv);
@@ -272,6 +278,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 fo.l[ft][rb] = __builtin_bit_cast(half8, vl);
                 if (rb + 1 < RB) rot(cv, sv, ex, ey);
             }
+        };
+        auto gen_f_pixel = [&](int st, int ft, int j, fops &fo) {
+            const pix_par &pf = sPar[(st / kSPB) & 1][(st % kSPB) * kKP + 8 * ft + 4 * g + j];
+            gen_f_reg(st, ft, j, pf.psi_f, pf.b, fo);
         };
 
         float2 *part = reinterpret_cast<float2 *>(J.partial) +
@@ -317,8 +327,12 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
         // the other evaluates phasors.  The first wave evaluates F of the
         // next step after its products, the second F of the current step
         // before them; either way the F registers are dead when they are
-        // rewritten, so one set suffices.  (Without the phase shift the
-        // steps run step_pipe below.)
+        // rewritten, so one set suffices.  The vector part first issues all
+        // its parameter reads (the D pixel's and the eight F pixels') and
+        // only then starts the arithmetic, so that it waits for LDS once
+        // instead of once per pixel pair; in the first wave that is after
+        // its products, which then start right after the barrier.  (Without
+        // the phase shift the steps run step_pipe below.)
         // What is evaluated after the last step is never used.
         constexpr int NG = 2 * CB;                  // groups per step
         constexpr int FG = NG - DPT;                // slices evaluating F
@@ -330,12 +344,29 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
             const int s1 = st + 1;
             float al[DPT];
             if constexpr (BS) load_al(s1, al);
-            const pix_par &pd = sPar[(s1 / kSPB) & 1][(s1 % kSPB) * kKP + q];
-            const float fd = frac32(pd.beta * (double)(l0 + lq));
-            float u = pd.a * __builtin_amdgcn_cosf(fd);
-            float w = pd.a * __builtin_amdgcn_sinf(fd);
-            pin(u, w);
-            const float cx = pd.srx, cy = pd.sry;
+            // parameters of the vector part, all read from LDS before any of
+            // its arithmetic: D of step s1, F pixels of step fstep
+            double dbeta = 0.0, fpsi[8], fbb[8];
+            float da = 0.f, cx = 0.f, cy = 0.f, u = 0.f, w = 0.f;
+            auto fetch = [&] {
+                const pix_par &pd = sPar[(s1 / kSPB) & 1][(s1 % kSPB) * kKP + q];
+                dbeta = pd.beta;
+                da = pd.a;
+                cx = pd.srx;
+                cy = pd.sry;
+#pragma unroll
+                for (int fp = 0; fp < 8; ++fp) {
+                    const pix_par &pf = sPar[(fstep / kSPB) & 1][(fstep % kSPB) * kKP + 8 * (fp >> 2) + 4 * g + (fp & 3)];
+                    fpsi[fp] = pf.psi_f;
+                    fbb[fp] = pf.b;
+                }
+            };
+            auto d_start = [&] {
+                const float fd = frac32(dbeta * (double)(l0 + lq));
+                u = da * __builtin_amdgcn_cosf(fd);
+                w = da * __builtin_amdgcn_sinf(fd);
+                pin(u, w);
+            };
             char (&dbn)[2][DBYTES] = decltype(nxt)::value ? sD1 : sD0;
             char *dwh = dbn[0] + lq * kCS + q * 4;
             char *dwl = dbn[1] + lq * kCS + q * 4;
@@ -383,7 +414,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
 #pragma unroll
                     for (int k8 = 0; k8 < FPG; ++k8) {
                         const int fp = (gi - DPT) * FPG + k8;  // F pixel 0..7 of step fstep
-                        if (fp < 8) gen_f_pixel(fstep, fp >> 2, fp & 3, fn);
+                        if (fp < 8) gen_f_reg(fstep, fp >> 2, fp & 3, fpsi[fp], fbb[fp], fn);
                     }
                 }
             };
@@ -392,6 +423,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                 // matrix work, so that it complements the first wave (with
                 // strengths per block the F slices go first, giving the
                 // strength loads time to arrive)
+                fetch();
+                __builtin_amdgcn_sched_barrier(0);
+                d_start();
 #pragma unroll
                 for (int i = 0; i < NG; ++i) valu_slice(BS ? (i + DPT) % NG : i);
                 __builtin_amdgcn_sched_barrier(0);
@@ -408,6 +442,9 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mfma_split16(rs_launch Lc)
                     mfma_group(gi);
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                fetch();
+                __builtin_amdgcn_sched_barrier(0);
+                d_start();
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) valu_slice(gi);
             }

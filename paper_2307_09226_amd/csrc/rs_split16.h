@@ -34,6 +34,22 @@ __device__ __forceinline__ rs_half2v rs_lo2(float x, float y, rs_half2v h)
     return __builtin_bit_cast(rs_half2v, r);
 }
 
+// (x, y) -> (-y, x): a packed fp16 pair times j.  One packed multiply by
+// 1.0 with the halves swapped (op_sel picks the high half for the low result,
+// op_sel_hi the low half for the high one) and the low result negated.
+// Multiplying by 1.0 and negating are exact, so applied to the split of
+// (x, y) it gives the split of (-y, x): rne16(-y) = -rne16(y) and
+// rne16(-y - rne16(-y)) = -rne16(y - rne16(y)), bit for bit except that a
+// zero lo half may come out as -0 where the direct split gives +0 (no sum
+// of products changes with the sign of a zero term).
+__device__ __forceinline__ rs_half2v rs_jmul(rs_half2v v)
+{
+    unsigned r;
+    asm("v_pk_mul_f16 %0, %1, 1.0 op_sel:[1,0] op_sel_hi:[0,0] neg_lo:[1,0]"
+        : "=v"(r) : "v"(__builtin_bit_cast(unsigned, v)));
+    return __builtin_bit_cast(rs_half2v, r);
+}
+
 __device__ __forceinline__ unsigned rs_bits(rs_half2v v) { return __builtin_bit_cast(unsigned, v); }
 
 // (u + j w) * (rx + j ry) in binary32

@@ -5,6 +5,7 @@
 //   prim_fract      __builtin_amdgcn_fract (v_fract_f64) and rs_frac
 //   prim_sincos     the binary32 hardware sin / cos, input in revolutions
 //   prim_split16    the fp16 hi / lo split of a binary32 pair
+//   prim_split16j   that split times j (rs_jmul): the split of (-y, x)
 // Every function enqueues one kernel on `stream` and returns 0, or the HIP
 // error code of the launch.  All pointers are device memory of n elements
 // (prim_distance: ant holds 3 doubles).  Built with the library's flags.
@@ -57,6 +58,19 @@ __global__ void k_split16(const float2 *in, unsigned *hi, unsigned *lo, int n)
     }
 }
 
+// as k_split16, then both packed pairs times j
+__global__ void k_split16j(const float2 *in, unsigned *hi, unsigned *lo, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        float x = in[i].x, y = in[i].y;
+        rs_pin(x, y);
+        const rs_half2v h = rs_hi2(x, y);
+        hi[i] = rs_bits(rs_jmul(h));
+        lo[i] = rs_bits(rs_jmul(rs_lo2(x, y, h)));
+    }
+}
+
 int launched() { return (int)hipGetLastError(); }
 
 unsigned blocks(int n) { return (unsigned)((n + 255) / 256); }
@@ -96,6 +110,14 @@ extern "C" int prim_split16(const float *in, unsigned *hi, unsigned *lo, int n, 
 {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(k_split16, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float2 *>(in), hi, lo, n);
+    return launched();
+}
+
+extern "C" int prim_split16j(const float *in, unsigned *hi, unsigned *lo, int n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_split16j, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream,
                        reinterpret_cast<const float2 *>(in), hi, lo, n);
     return launched();
 }

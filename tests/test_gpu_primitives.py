@@ -11,7 +11,8 @@ with the library's flags by build.py; librs.so is not involved):
   largest error against the binary64 sin / cos of 2 pi x is bounded by
   SINCOS_MAX_ABS (the bound the matrix-core form's error budget uses);
 * the fp16 split of a binary32 pair is hi = rne16(x), lo = rne16(x - hi),
-  bitwise equal to NumPy's round-to-nearest-even conversions.
+  bitwise equal to NumPy's round-to-nearest-even conversions, and that
+  split times j is the split of (-y, x) (the imaginary D column).
 """
 import ctypes
 import os
@@ -42,7 +43,9 @@ def prims():
     lib.prim_fract.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
     lib.prim_sincos.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.prim_split16.argtypes = [vp, vp, vp, ctypes.c_int, vp]
-    for f in (lib.prim_distance, lib.prim_sqrt, lib.prim_fract, lib.prim_sincos, lib.prim_split16):
+    lib.prim_split16j.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    for f in (lib.prim_distance, lib.prim_sqrt, lib.prim_fract, lib.prim_sincos, lib.prim_split16,
+              lib.prim_split16j):
         f.restype = ctypes.c_int
     return lib
 
@@ -176,3 +179,36 @@ def test_split16_round_to_nearest_even(prims):
     big = np.abs(x) >= 2.0 ** -2
     rec = want_hi.astype(np.float64) + want_lo.astype(np.float64)
     assert np.all(np.abs(rec - x)[big] <= 2.0 ** -22 * np.abs(x.astype(np.float64))[big])
+
+
+def test_split16_times_j(prims):
+    """The imaginary D column (-w, u) is the split of (u, w) times j: hi
+    halves bitwise rne16(-w), rne16(u); lo halves rne16(-w - rne16(-w)),
+    rne16(u - rne16(u)) equal in value, bitwise wherever nonzero (a zero lo
+    half may carry either sign).  Pairs include exact fp16 values, whose lo
+    halves are zero, and fp16 subnormal residuals."""
+    import torch
+    rng = np.random.default_rng(16)
+    n = 1 << 18
+    unit = rng.uniform(-1.0, 1.0, n)
+    scaled = rng.uniform(-1.0, 1.0, n) * 2.0 ** rng.integers(-14, 15, n)
+    tiny = rng.uniform(-1.0, 1.0, n // 4) * 2.0 ** rng.integers(-30, -14, n // 4)
+    exact = rng.uniform(-1.0, 1.0, n // 4).astype(np.float16).astype(np.float64)
+    x = np.concatenate([unit, scaled, tiny, exact, [0.0, -0.0, 1.0, -1.0, 65504.0, 2.0 ** -24]])
+    x = rng.permutation(x).astype(np.float32)
+    if x.size % 2:
+        x = np.append(x, np.float32(0.5))
+    pairs = x.size // 2
+    hi, lo = _empty(pairs, torch.int32), _empty(pairs, torch.int32)
+    _run(prims.prim_split16j, _dev(x), hi, lo, pairs)
+    got_hi = hi.cpu().numpy().view(np.float16)  # (-y, x) per pair
+    got_lo = lo.cpu().numpy().view(np.float16)
+    xy = x.reshape(-1, 2)
+    xj = np.stack([-xy[:, 1], xy[:, 0]], axis=1).reshape(-1)  # (-y, x), binary32
+    want_hi = xj.astype(np.float16)
+    want_lo = (xj - want_hi.astype(np.float32)).astype(np.float16)
+    assert np.array_equal(got_hi.view(np.uint16), want_hi.view(np.uint16))
+    assert np.array_equal(got_lo, want_lo)  # by value: +0 == -0
+    nz = want_lo != 0
+    assert np.array_equal(got_lo.view(np.uint16)[nz], want_lo.view(np.uint16)[nz])
+    assert np.count_nonzero(~nz) > n // 8  # the zero-lo case is exercised
