@@ -39,8 +39,8 @@ FLOP_PLAIN = 8         # one binary64 complex MAC
 # the kernel sources they were taken on; any change to those sources turns
 # the figure into null until the counters are taken again.
 TRAFFIC = {"sources": ("rs_mfma.hip", "rs_device.h", "rs_internal.h", "rs_split16.h"),
-           "sources_sha256": "e38527d34e41833d95c47c23b1e0ce06461b849efc0bbb15cba394fd0676aa8b",
-           "fetch_bytes": 2.0 * 5299 * 1024, "write_bytes": 65380 * 1024}
+           "sources_sha256": "2531908b0f6cc278ab62095a58bc7aa1b4f65346f67c1a998c49ce053131e591",
+           "fetch_bytes": 2.0 * 5289 * 1024, "write_bytes": 65362 * 1024}
 # The same for one rs_range_doppler_ws call on the 100-frame walk (k_rd_fused,
 # k_rd_merge, k_rd_peak summed).
 RD_TRAFFIC = {"sources": ("rs_rd.hip", "rs_fft.h"),
