@@ -66,6 +66,49 @@ def test_alone_vs_mix_bitwise_and_parity():
     sess.close()
 
 
+# Full-size requests of the serving pool (base seed 1000): the four largest
+# (2.95e12, 1.62e12, 1.17e12 and 1.02e12 terms, 192 channels each) and four
+# smaller ones, 3x4 and 1x4 arrays among them.
+FULL_MIX = (17, 31, 10, 41, 32, 3, 5, 8)
+
+
+def test_full_size_mix_bitwise_and_parity():
+    """A mix of full-size pool requests served together (slices of the
+    default size, shortest-remaining shares) gives each request the cube it
+    gets alone, bit for bit, and sampled entries of every request match the
+    oracle."""
+    import torch
+    rs = _rs()
+    reqs = [scenes.serving_requests(1, start=i)[0] for i in FULL_MIX]
+    assert max(q.radar.C * q.radar.Ns * q.radar.L * q.pixels.P for q in reqs) > 2.9e12
+    plans = [rs.rs_cube_plan(q.radar, rs.RS_FORM_MFMA_SPLIT16, rs.RS_C64, max_pixels=q.pixels.P)
+             for q in reqs]
+    dpx = [rs.DevicePixels.from_host(q.pixels) for q in reqs]
+    alone = []
+    for p, d in zip(plans, dpx):
+        c = rs.new_cube(p)
+        rs.rs_beat_synthesize(p, d, c)
+        alone.append(c)
+    torch.cuda.synchronize()
+    sess = rs.Session(hbm_budget=12 << 30, max_slots=8)
+    cubes = [rs.new_cube(p) for p in plans]
+    tickets = [sess.submit(p, d, c) for p, d, c in zip(plans, dpx, cubes)]
+    states = _wait(sess, tickets, timeout=120.0)
+    assert all(s == rs.RS_REQ_DONE for s in states.values())
+    st = sess.stats()
+    assert st["done"] == len(reqs) and st["launches"] >= len(reqs)
+    for i, (a, b) in enumerate(zip(alone, cubes)):
+        assert torch.equal(a, b), FULL_MIX[i]
+    for i, q in enumerate(reqs):
+        c, l, n = sample_indices(q.radar.cube_shape(), 128, seed=100 + i)
+        ref = oracle.entries(q.radar, q.pixels, c, l, n)
+        rel, mx = errors(cubes[i].cpu().numpy()[c, l, n], ref)
+        print(f"request {FULL_MIX[i]}: C={q.radar.C} Ns={q.radar.Ns} L={q.radar.L} P={q.pixels.P} "
+              f"relL2={rel:.3e} maxabs={mx:.3e}", flush=True)
+        assert rel <= GATE_MFMA and mx <= GATE_MFMA, FULL_MIX[i]
+    sess.close()
+
+
 def test_admission_respects_budget_and_backpressure():
     import torch
     rs = _rs()
