@@ -499,7 +499,8 @@ rs_status rs_range_doppler_ws(rs_plan *plan, const void *cubes, int32_t nframes,
 /* Per-launch timing of the main (contraction) kernel with HIP events, for
  * profiling.  A timer attached to the calling thread records an event pair
  * around every main-kernel launch made by rs_beat_synthesize* and
- * rs_beat_synthesize_batch from that thread, on the launch's stream, until
+ * rs_beat_synthesize_batch, and around the ray-cast kernel of
+ * rs_render_scenes, from that thread, on the launch's stream, until
  * `capacity` launches are recorded.  Create and read on the plan's device. */
 typedef struct rs_kernel_timer rs_kernel_timer;
 

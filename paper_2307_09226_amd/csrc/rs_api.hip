@@ -200,22 +200,32 @@ extern "C" void rs_kernel_timer_destroy(rs_kernel_timer *t)
     delete t;
 }
 
+bool rs_timer_begin(hipStream_t st)
+{
+    rs_kernel_timer *tm = tl_timer;
+    if (!tm || tm->used >= tm->cap) return false;
+    (void)hipEventRecord(tm->ev[2 * tm->used], st);
+    return true;
+}
+
+void rs_timer_end(hipStream_t st)
+{
+    rs_kernel_timer *tm = tl_timer;
+    (void)hipEventRecord(tm->ev[2 * tm->used + 1], st);
+    tm->used++;
+}
+
 rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, bool block_strength, int grid, hipStream_t st)
 {
     if (L.total <= 0) return RS_OK;
-    rs_kernel_timer *tm = tl_timer;
-    const bool timed = tm && tm->used < tm->cap;
-    if (timed) (void)hipEventRecord(tm->ev[2 * tm->used], st);
+    const bool timed = rs_timer_begin(st);
     if (pl->form == RS_FORM_FP64_DIRECT)
         rs_launch_plain(L, pl->tl, grid, st);
     else
         rs_launch_mfma(L, pl->wn, pl->tl, pl->nw, pl->interleave != 0, block_strength, grid, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rs_fail(RS_E_DEVICE, "main kernel launch: %s", hipGetErrorString(e));
-    if (timed) {
-        (void)hipEventRecord(tm->ev[2 * tm->used + 1], st);
-        tm->used++;
-    }
+    if (timed) rs_timer_end(st);
     return RS_OK;
 }
 

@@ -60,6 +60,11 @@ rs_status rs_launch_scale_checked(const rs_launch &L, bool block_strength, hipSt
 rs_job rs_make_job(const rs_plan *pl, const rs_pixels *px, void *cube, void *partial,
                    int32_t S, int32_t chunk);
 rs_status rs_check_pixels(const rs_plan *pl, const rs_pixels *px);
+// The calling thread's kernel timer (rs_kernel_timer_attach): an event
+// before a launch on st when the timer has room (returns whether it took
+// one), and the closing event after it.
+bool rs_timer_begin(hipStream_t st);
+void rs_timer_end(hipStream_t st);
 // block_strength: some job of the launch has strengths per block
 rs_status rs_launch_main(const rs_plan *pl, const rs_launch &L, bool block_strength, int grid, hipStream_t st);
 rs_status rs_launch_reduce_checked(const rs_plan *pl, const rs_launch &L, hipStream_t st);

@@ -1,9 +1,10 @@
 // Synthetic scenes on the device: each pixel of a g_az x g_el grid casts a
 // ray from the origin into an axis-aligned room and an optional ellipsoid
 // pedestrian (the stand-in for the rendered image whose pixels the paper
-// turns into scatterers, Sec. II).  One thread per pixel, binary64
-// geometry, float32 structure-of-arrays output: memory bound (20 bytes
-// written and 4 read per pixel).
+// turns into scatterers, Sec. II).  A thread takes one pixel of a few
+// frames (its ray direction, two binary64 sincospi, is shared by them);
+// binary64 geometry, float32 structure-of-arrays output (20 bytes written
+// and 4 read per pixel and frame).
 #include "rs_api_internal.h"
 
 #include <cmath>
@@ -11,22 +12,13 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_render(const rs_scene *scenes, int64_t P, int64_t total, int g_az,
-                                                int g_el, const float *noise, float *ox, float *oy, float *oz,
-                                                float *oamp, float *ovr)
+constexpr int kFramesPerThread = 4;  // frames one thread casts along its pixel's ray
+
+// The ray of one pixel against one frame's room and pedestrian; writes the
+// pixel's scatterer at index g of the output arrays.
+__device__ __forceinline__ void cast(const rs_scene &S, const double (&u)[3], int64_t g, const float *noise,
+                                     float *ox, float *oy, float *oz, float *oamp, float *ovr)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= total) return;
-    const int64_t f = g / P, p = g % P;
-    const rs_scene &S = scenes[f];
-    const int i = (int)(p % g_az), j = (int)(p / g_az);
-    // ray direction of the pixel centre (angles in degrees / 180 = half turns)
-    const double az = (-60.0 + 120.0 * ((double)i + 0.5) / (double)g_az) / 180.0;
-    const double el = (-30.0 + 60.0 * ((double)j + 0.5) / (double)g_el) / 180.0;
-    double saz, caz, sel, cel;
-    sincospi(az, &saz, &caz);
-    sincospi(el, &sel, &cel);
-    const double u[3] = {cel * saz, cel * caz, sel};
     // nearest wall: planes x = +-W/2, y = D, z = +-H/2
     const double inf = __builtin_huge_val();
     const double tx = u[0] > 0 ? (S.room_w / 2) / u[0] : (u[0] < 0 ? (-S.room_w / 2) / u[0] : inf);
@@ -79,6 +71,28 @@ __global__ __launch_bounds__(256) void k_render(const rs_scene *scenes, int64_t 
     ovr[g] = (float)v;
 }
 
+// Thread = (pixel p, group of kFramesPerThread frames): the pixel's ray
+// direction is evaluated once and cast into each frame of the group.
+__global__ __launch_bounds__(256) void k_render(const rs_scene *scenes, int64_t P, int nframes, int64_t threads,
+                                                int g_az, int g_el, const float *noise, float *ox, float *oy,
+                                                float *oz, float *oamp, float *ovr)
+{
+    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gi >= threads) return;
+    const int64_t p = gi % P;
+    const int f0 = (int)(gi / P) * kFramesPerThread;
+    const int i = (int)(p % g_az), j = (int)(p / g_az);
+    // ray direction of the pixel centre (angles in degrees / 180 = half turns)
+    const double az = (-60.0 + 120.0 * ((double)i + 0.5) / (double)g_az) / 180.0;
+    const double el = (-30.0 + 60.0 * ((double)j + 0.5) / (double)g_el) / 180.0;
+    double saz, caz, sel, cel;
+    sincospi(az, &saz, &caz);
+    sincospi(el, &sel, &cel);
+    const double u[3] = {cel * saz, cel * caz, sel};
+    const int f1 = min(nframes, f0 + kFramesPerThread);
+    for (int f = f0; f < f1; ++f) cast(scenes[f], u, (int64_t)f * P + p, noise, ox, oy, oz, oamp, ovr);
+}
+
 bool pos_finite(double v) { return std::isfinite(v) && v > 0.0; }
 
 }  // namespace
@@ -111,11 +125,13 @@ extern "C" rs_status rs_render_scenes(const rs_scene *scenes, int32_t nframes, i
     hipError_t e = hipMemcpyAsync(d, scenes, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "scene copy: %s", hipGetErrorString(e));
     if (s == RS_OK) {
-        const int64_t total = P * nframes;
-        hipLaunchKernelGGL(k_render, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, d, P, total, g_az,
-                           g_el, noise, x, y, z, amp, vr);
+        const int64_t threads = P * ((nframes + kFramesPerThread - 1) / kFramesPerThread);
+        const bool timed = rs_timer_begin(st);
+        hipLaunchKernelGGL(k_render, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, d, P, nframes,
+                           threads, g_az, g_el, noise, x, y, z, amp, vr);
         e = hipGetLastError();
         if (e != hipSuccess) s = rs_fail(RS_E_DEVICE, "render launch: %s", hipGetErrorString(e));
+        else if (timed) rs_timer_end(st);
     }
     e = hipFreeAsync(d, st);
     if (e != hipSuccess && s == RS_OK) s = rs_fail(RS_E_DEVICE, "hipFreeAsync: %s", hipGetErrorString(e));
