@@ -48,6 +48,15 @@ RD_TRAFFIC = {"sources": ("rs_rd.hip", "rs_fft.h"),
               "fetch_bytes": 2.0 * (158861 + 20530 + 52) * 1024, "write_bytes": (42880 + 12825 + 55) * 1024}
 
 
+# VALU wave-instructions per launch of k_render on the 100-frame walk
+# (rocprofv3 --pmc SQ_INSTS_VALU); like the records above, null once its
+# source changes.  The kernel is bound by vector issue (binary64 geometry):
+# 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction.
+RENDER_VALU = {"sources": ("rs_scene.hip",),
+               "sources_sha256": "d633d719d222e4f30f07c373dc0120ef798efeae22df77f242c89bcfeabb7333",
+               "valu_instr": 25334220}
+PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4
+
 # Offered load of the serving leg, frozen so that latencies stay comparable
 # between runs: 0.6 x the capacity measured with the whole 48-request pool
 # queued at once (4.44e13 terms/s) / the pool's mean request (1.94e11 terms).
@@ -497,16 +506,25 @@ def doppler_time_leg(rs, scenes, dev, timer):
             "device_rendered": {
                 "render_ms": render_ms,
                 "render_kernel_ms": render_kernel_ms,
-                "render_roofline": {"bound": "hbm",
-                                    "achieved": render_bytes / (render_kernel_ms * 1e-3) / 1e9,
-                                    "peak": 8000.0, "unit": "GB/s",
-                                    "frac": render_bytes / (render_kernel_ms * 1e-3) / 8e12,
-                                    "time": "k_render alone (HIP events around the launch); render_ms is "
-                                            "the whole call from Python, host work included"},
+                "render_roofline": render_roofline(render_bytes, render_kernel_ms),
                 "render_synth_rd_ms": pwall * 1e3 / 3,
                 "E_velo_mps": float(np.mean(err2)), "max_abs_error_mps": float(err2.max())},
             "v_est": [round(float(v), 3) for v in v_est],
             "v_true": [round(float(v), 3) for v in cw.v_radial]}
+
+
+def render_roofline(nbytes, kernel_ms):
+    """k_render against the vector issue rate (measured instruction count),
+    with its HBM fraction beside it."""
+    if not kernel_ms:
+        return None
+    instr = RENDER_VALU["valu_instr"] if sources_sha256(RENDER_VALU["sources"]) == RENDER_VALU["sources_sha256"]         else None
+    rate = instr / (kernel_ms * 1e-3) if instr else None
+    return {"bound": "alu", "achieved": rate / 1e9 if rate else None, "peak": PEAK_VALU_ISSUE / 1e9,
+            "unit": "G wave64 VALU instructions/s", "frac": rate / PEAK_VALU_ISSUE if rate else None,
+            "hbm_gbps": nbytes / (kernel_ms * 1e-3) / 1e9, "hbm_frac": nbytes / (kernel_ms * 1e-3) / 8e12,
+            "time": "k_render alone (HIP events around the launch); render_ms is the whole call from "
+                    "Python, host work included"}
 
 
 def copy_probe(mib):
