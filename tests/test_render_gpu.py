@@ -50,13 +50,16 @@ def test_matches_cpu_renderer(grid, ped):
 def test_batch_of_walk_frames_and_no_noise():
     import torch
     rs = _rs()
-    cw = scenes.circle_walk(frame_ids=[0, 17, 50, 83], grid=96)
+    # five frames: a thread casts its pixel into up to four frames, so the
+    # fifth starts a second, ragged group
+    ids = [0, 17, 50, 83, 99]
+    cw = scenes.circle_walk(frame_ids=ids, grid=96)
     room = scenes.Room(W=12.0, D=10.0)
     structs = [rs.scene_struct(room, scenes.Pedestrian(centre=c, velocity=v))
                for c, v in zip(cw.centres, cw.velocities)]
     frames = rs.rs_render_scenes(structs, 96, 96)   # noise = 1
     torch.cuda.synchronize()
-    for k, f in enumerate([0, 17, 50, 83]):
+    for k, f in enumerate(ids):
         ref = scenes.render(_OnesRng(), room, scenes.Pedestrian(centre=cw.centres[k], velocity=cw.velocities[k]),
                             96, 96)
         _compare(frames[k], ref)
