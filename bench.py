@@ -39,7 +39,7 @@ FLOP_PLAIN = 8         # one binary64 complex MAC
 # the kernel sources they were taken on; any change to those sources turns
 # the figure into null until the counters are taken again.
 TRAFFIC = {"sources": ("rs_mfma.hip", "rs_device.h", "rs_internal.h", "rs_split16.h"),
-           "sources_sha256": "2531908b0f6cc278ab62095a58bc7aa1b4f65346f67c1a998c49ce053131e591",
+           "sources_sha256": "44849d3c15d1a5854c90d8e613516197a2a84f380176b3013655c7f83f33458a",
            "fetch_bytes": 2.0 * 5289 * 1024, "write_bytes": 65362 * 1024}
 # The same for one rs_range_doppler_ws call on the 100-frame walk (k_rd_fused,
 # k_rd_merge, k_rd_peak summed).

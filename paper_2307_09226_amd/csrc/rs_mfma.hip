@@ -19,10 +19,12 @@
 //   item  = (channel, n tile of NW*WN rows, l tile of TL columns, pixel chunk)
 //   wave  = WN rows x TL complex columns; WN/32 x 2TL/32 accumulator blocks
 //   F     = A operand, evaluated by each lane for exactly the rows and pixels
-//           it feeds to the matrix core (registers only, double-buffered so
-//           the next step's phasors are computed while the matrix cores run)
+//           it feeds to the matrix core (registers only: two sets in the
+//           pipelined schedule, one in the phase-shifted one, where a wave
+//           rewrites its F registers only around its own products)
 //   D     = B operand, evaluated once per workgroup per 16-pixel step into
-//           double-buffered LDS (both column arrangements, hi and lo)
+//           double-buffered LDS (both column arrangements, hi and lo; the
+//           imaginary arrangement's split is the real one's times j)
 // Two step schedules.  Phase-shifted waves (NW = 8): the two waves of a SIMD
 // run their matrix and vector parts in opposite order, so the hardware
 // interleaves one wave's matrix instructions with the other's phasor
@@ -32,7 +34,8 @@
 // one slice apart so that no wave waits on its own vector results.
 // Phasor cost: per pixel and lane one binary64-reduced phasor; the other rows
 // of the lane follow by binary32 rotation with exp(j2pi frac(32 b)), and the
-// slow-time phasors of a thread by rotation with exp(j2pi frac(16 beta)) --
+// slow-time phasors of a thread by rotation with exp(j2pi frac(LQ beta)), LQ
+// the number of D threads per pixel (16 or 32) --
 // every rotation factor is itself reduced in binary64, so the error stays at
 // a few binary32 ulp (well below the fp16 hi/lo resolution of ~2^-22).
 //
