@@ -9,8 +9,9 @@
 //
 // Work item = (channel, 64-row n tile, TL-column l tile, pixel chunk).  Per
 // step of 16 pixels the workgroup evaluates the 16 x 64 F and 16 x TL D
-// phasors once into LDS; each thread then owns a 4 (n) x TL/16 (l) block of
-// binary64 accumulators.  A thread evaluates a run of consecutive phasors of
+// phasors once into LDS (each of a pixel's 16 threads finds the pixel's
+// phase arguments itself, so the step has no serial parameter stage); each
+// thread then owns a 4 (n) x TL/16 (l) block of binary64 accumulators.  A thread evaluates a run of consecutive phasors of
 // one pixel: the first directly (binary64 sincospi of the reduced phase),
 // the others by binary64 rotation with exp(j2pi frac(b)) or
 // exp(-j2pi frac(beta)), at most 7 rotations (~1e-15 relative).  With
@@ -31,7 +32,6 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
     constexpr int NJ = TL / 16;
     __shared__ double2 sF[kKP][kTN];
     __shared__ double2 sD[kKP][TL];
-    __shared__ double sPsi[kKP], sB[kKP], sBeta[kKP], sA[kKP];
     __shared__ rs_item_consts sK;
     __shared__ int64_t s_item;
 
@@ -52,19 +52,18 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
         // every reader of the previous item's sK has passed a barrier since
         if (tid == 0) rs_item_consts_of(J, m, r, sK);
         __syncthreads();
-        // raw values of this thread's pixel of the next step (threads < kKP),
-        // loaded a step ahead; the index is clamped into the chunk and the
-        // pixel's validity decided when it is used
+        // raw values of this thread's pixel of the next step (the 16 threads
+        // of a pixel load the same values), loaded a step ahead; the index is
+        // clamped into the chunk and the pixel's validity decided when it is
+        // used
         float nx, ny, nz, na, nv;
         auto fetch = [&](int64_t p0) {
-            if (tid < kKP) {
-                const int64_t p = min(p0 + tid, pe - 1);
-                nx = rs_gload(sK.x, p);
-                ny = rs_gload(sK.y, p);
-                nz = rs_gload(sK.z, p);
-                na = rs_gload(sK.amp, p);
-                nv = rs_gload(sK.vr, p);
-            }
+            const int64_t p = min(p0 + (tid >> 4), pe - 1);
+            nx = rs_gload(sK.x, p);
+            ny = rs_gload(sK.y, p);
+            nz = rs_gload(sK.z, p);
+            na = rs_gload(sK.amp, p);
+            nv = rs_gload(sK.vr, p);
         };
         fetch(pb);
 
@@ -75,32 +74,22 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
             for (int j = 0; j < NJ; ++j) acc[i][j] = make_double2(0.0, 0.0);
 
         for (int64_t p0 = pb; p0 < pe; p0 += kKP) {
-            if (tid < kKP) {
-                const int64_t p = p0 + tid;
-                if (p < pe) {
-                    double psi, b, beta;
-                    rs_chan_args(sK, nx, ny, nz, nv, m, sK.tx, sK.rx, &psi, &b, &beta);
-                    sPsi[tid] = rs_frac(psi);
-                    sB[tid] = b;
-                    sBeta[tid] = beta;
-                    sA[tid] = (double)na;
-                } else {
-                    sPsi[tid] = 0.0;
-                    sB[tid] = 0.0;
-                    sBeta[tid] = 0.0;
-                    sA[tid] = 0.0;
-                }
-            }
-            fetch(p0 + kKP);
-            __syncthreads();
             {
-                // thread = (pixel q, run r of consecutive rows / columns)
+                // thread = (pixel q, run r of consecutive rows / columns); each
+                // of the pixel's 16 threads finds its phase arguments
                 const int q = tid >> 4, r = tid & 15;
+                double psi_f = 0.0, b = 0.0, beta = 0.0, a = 0.0;
+                if (p0 + q < pe) {
+                    double psi;
+                    rs_chan_args(sK, nx, ny, nz, nv, m, sK.tx, sK.rx, &psi, &b, &beta);
+                    psi_f = rs_frac(psi);
+                    a = (double)na;
+                }
+                fetch(p0 + kKP);
                 // fast-time phasors F = exp(j 2pi phi), phi = wrap(psi_f + frac(b n)),
                 // rows n0 + 4r .. n0 + 4r + 3
                 constexpr int FR = kTN / 16;
-                const double b = sB[q];
-                double phi = sPsi[q] + rs_frac(b * (double)(n0 + FR * r));
+                double phi = psi_f + rs_frac(b * (double)(n0 + FR * r));
                 phi = phi - __builtin_floor(phi + 0.5);
                 double fs, fc, rs_, rc;
                 sincospi(2.0 * phi, &fs, &fc);
@@ -115,7 +104,6 @@ __global__ __launch_bounds__(256, 2) void k_plain_fp64(rs_launch Lc)
                 // slow-time phasors D = a exp(-j 2pi frac(beta l)), columns
                 // l0 + DR r .. l0 + DR r + DR - 1
                 constexpr int DR = TL / 16;
-                const double beta = sBeta[q], a = sA[q];
                 double ds, dc, ts, tc;
                 sincospi(2.0 * rs_frac(beta * (double)(l0 + DR * r)), &ds, &dc);
                 sincospi(2.0 * rs_frac(beta), &ts, &tc);
